@@ -1,0 +1,172 @@
+/* wvl.h -- C ABI of libwvl: the local Hamiltonian of the Daubechies-wavelet
+ * Kohn-Sham method (Genovese et al., "Density Functional Theory calculation on
+ * many-cores hybrid CPU-GPU architectures") on one AMD MI355X (gfx950) GPU.
+ *
+ * Conventions common to every call
+ * --------------------------------
+ * Grids.  One orbital lives on a periodic coarse grid of n1 x n2 x n3 points
+ * (axis 1 fastest).  Its fine grid (spacing h/2, Sec. 2.1, Eq. "wavefhigh")
+ * has m_a = 2 n_a points per axis and is stored as a C-order (m3, m2, m1)
+ * array.  Coarse coefficients (one scaling + seven wavelet components per
+ * coarse point, Sec. 2.1, Eq. "wavef0") use the same (m3, m2, m1) array with
+ * the two levels interleaved along every axis: along axis a, index 2i holds
+ * the scaling part and 2i+1 the wavelet part of coarse point i; component
+ * mu = b1 + 2 b2 + 4 b3 of coarse point (i1, i2, i3) sits at
+ * (2 i3 + b3, 2 i2 + b2, 2 i1 + b1).  Boundary conditions are periodic
+ * (Sec. 3.1).
+ *
+ * Batches.  A plan describes a batch of orbitals (Sec. 5.1: every orbital is
+ * processed independently).  Batch arrays are packed buffers: orbital b
+ * occupies elements [off_b, off_b + m1 m2 m3).  The element type depends on
+ * the plan precision: WVL_F64 -> double; WVL_F32 -> float; WVL_F32C -> two
+ * float planes, hi then lo, each of wvl_plan_elements() elements (value =
+ * hi + lo).  Potentials, densities, energies and overlap matrices are always
+ * double.
+ *
+ * Memory.  Every data pointer is a DEVICE pointer owned by the caller; the
+ * library neither frees nor keeps it after the call returns (except the graph
+ * cache of WVL_USE_GRAPH, which records pointers and re-records when they
+ * change).  `ws` is caller-owned device workspace of wvl_plan_workspace()
+ * bytes (256-byte aligned).  `stream` is a hipStream_t (NULL = default stream).
+ *
+ * Errors.  Every call returns a wvl_status.  Arguments are checked before any
+ * HIP call is made; HIP failures map to WVL_EHIP.  Calls are asynchronous on
+ * `stream`; device-side failures (a non-positive pivot in the Cholesky step)
+ * are reported by wvl_plan_sync().  wvl_last_error() returns a thread-local
+ * message about the last failure.  No call aborts the process.
+ */
+#ifndef WVL_PUBLIC_API_H_
+#define WVL_PUBLIC_API_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  WVL_OK = 0,
+  WVL_EINVAL = -1,       /* bad argument (null pointer, bad size, aliasing ...) */
+  WVL_EUNSUPPORTED = -2, /* valid but not supported by this plan              */
+  WVL_ENOMEM = -3,       /* device allocation failed                           */
+  WVL_EHIP = -4,         /* HIP runtime error                                  */
+  WVL_ETIMEOUT = -5,     /* device-side wait exceeded its bound                */
+  WVL_ENODEV = -6        /* no usable GPU (also: dry plans on a host)          */
+} wvl_status;
+
+typedef enum { WVL_F64 = 0, WVL_F32 = 1, WVL_F32C = 2 } wvl_prec;
+
+/* plan flags */
+#define WVL_SHARED_V   1u  /* all orbitals share one potential (and one grid)   */
+#define WVL_USE_GRAPH  2u  /* record wvl_local_hpsi in a hipGraph and replay it  */
+#define WVL_PERSISTENT 4u  /* run wvl_local_hpsi as one persistent kernel       */
+#define WVL_AUTOTUNE   8u  /* time the tile candidates at plan creation         */
+
+typedef struct {
+  int32_t n[3];     /* coarse dims n1, n2, n3 (>= 2 each); fine dims are 2n     */
+  int32_t reserved; /* must be 0                                               */
+  int64_t off;      /* element offset of the orbital in packed batch buffers   */
+  int64_t v_off;    /* element offset of its potential (ignored with SHARED_V) */
+  double hgrid[3];  /* fine grid spacing per axis (> 0)                         */
+  double occ;       /* occupation number f_i                                    */
+} wvl_orbital;
+
+typedef struct wvl_ctx wvl_ctx;
+typedef struct wvl_plan wvl_plan;
+
+/* Library context on GPU `device`.  device = -1 creates a "dry" context with
+ * no GPU: plans can be created and every argument check runs, but every call
+ * that would touch the GPU returns WVL_ENODEV.  Returns WVL_ENODEV if the GPU
+ * does not exist. */
+int wvl_create(wvl_ctx **ctx, int device);
+int wvl_destroy(wvl_ctx *ctx);
+
+/* Plan for a batch of `norb` orbitals in precision `prec`.  Copies the
+ * descriptor table to the device and fixes the tiling.  Requirements: n_a >= 2,
+ * orbitals do not overlap in the packed buffers; with WVL_SHARED_V all
+ * orbitals have the same dims.  wvl_overlap/wvl_orthonormalize need
+ * off_b = b * m1 m2 m3 (a dense [norb][M] matrix). */
+int wvl_plan_create(wvl_ctx *ctx, const wvl_orbital *orbs, int32_t norb, int32_t prec,
+                    uint32_t flags, wvl_plan **plan);
+int wvl_plan_destroy(wvl_plan *plan);
+/* bytes of workspace every call of this plan needs */
+int wvl_plan_workspace(const wvl_plan *plan, size_t *bytes);
+/* elements of one packed batch array (per plane for WVL_F32C) */
+int wvl_plan_elements(const wvl_plan *plan, int64_t *elems);
+/* points of the shared grid (WVL_SHARED_V plans), the length of V and rho */
+int wvl_plan_grid_points(const wvl_plan *plan, int64_t *points);
+
+/* Fast wavelet transform, coarse -> fine scaling coefficients (Sec. 2.1 and
+ * Sec. 2.4 step 2): per axis s[(2i + j) mod m] += h_j c_i + g_j d_i.
+ * `s` must not alias `c`. */
+int wvl_synthesis(wvl_plan *plan, const void *c, void *s, void *ws, void *stream);
+
+/* Inverse transform (Sec. 2.4 step 6): c_i = sum_j h_j s[(2i+j) mod m],
+ * d_i = sum_j g_j s[(2i+j) mod m].  `c` must not alias `s`. */
+int wvl_analysis(wvl_plan *plan, const void *s, void *c, void *ws, void *stream);
+
+/* Magic filter (Sec. 2.3, Eq. "magicfilter"): out[I] = sum_l w_l in[I-l] per
+ * axis; with transpose != 0 the transposed filter out[i] = sum_l w_l in[i+l]
+ * (Sec. 2.4 step 3c).  `out` must not alias `in`. */
+int wvl_magic_filter(wvl_plan *plan, const void *in, void *out, int transpose, void *ws,
+                     void *stream);
+
+/* Kinetic operator -1/2 nabla^2 on fine scaling coefficients (Sec. 2.2,
+ * Eqs. "kiner", "fprod"), with the accumulation of Sec. 3.4 (Eq. "kinetic1d"):
+ * out = Kin(s) + k0.  k0 may be NULL (taken as 0) or equal to out; `out` must
+ * not alias `s`. */
+int wvl_kinetic(wvl_plan *plan, const void *s, const void *k0, void *out, void *ws,
+                void *stream);
+
+/* Local density (Sec. 2.5): steps 2 and 3a of Sec. 2.4 followed by
+ * rho = [rho +] sum_b f_b psi_b^2 (Sec. 2, Eq. "density"), float64.
+ * WVL_SHARED_V plans only; accumulate != 0 adds to the existing rho. */
+int wvl_local_density(wvl_plan *plan, const void *c, double *rho, int accumulate, void *ws,
+                      void *stream);
+
+/* Local Hamiltonian (Sec. 2.4 steps 2-6): per orbital s = S c, psi = Omega s,
+ * y = pot_scale V psi, Hc = A (Omega^T y + kin_scale Kin s), written to hpsi
+ * (which may alias c).  Optional outputs (NULL to skip), all float64:
+ *   rho    sum_b f_b psi_b^2 (WVL_SHARED_V plans; overwritten)
+ *   e_loc  sum_r V rho (shared V) or sum_b f_b e_pot_b (per-orbital V)
+ *   e_kin  sum_b f_b <s_b, Kin s_b>
+ *   e_orb  [2 * norb]: e_pot_b = sum_r V psi_b^2, then e_kin_b = <s_b, Kin s_b>
+ * V: the shared potential (m3 m2 m1 doubles) or, without WVL_SHARED_V, a
+ * buffer holding orbital b's potential at v_off_b.  With pot_scale = kin_scale
+ * = 1 this is the plain local Hamiltonian; other scales give the weighted
+ * operator the energy gradients need. */
+int wvl_local_hpsi(wvl_plan *plan, const void *c, const double *V, double pot_scale,
+                   double kin_scale, void *hpsi, double *rho, double *e_loc, double *e_kin,
+                   double *e_orb, void *ws, void *stream);
+
+/* Overlap matrix S_ij = <c_i, c_j> over all coefficients (Sec. 2.6; Sec. 5
+ * step VIII), norb x norb float64, row-major.  Dense batches only. */
+int wvl_overlap(wvl_plan *plan, const void *c, double *S, void *ws, void *stream);
+
+/* Cholesky orthonormalisation (Sec. 5 step VIII): S = L L^T, c <- L^{-1} c
+ * (rows = orbitals), in place.  S and L (nullable, norb x norb row-major)
+ * receive the overlap matrix and the lower Cholesky factor.  A non-positive
+ * pivot is reported by wvl_plan_sync() as WVL_EINVAL. */
+int wvl_orthonormalize(wvl_plan *plan, void *c, double *S, double *L, void *ws, void *stream);
+
+/* Format conversion of `count` values between WVL_F64, WVL_F32 and WVL_F32C
+ * (hi/lo planes of `count` floats each); src and dst must not overlap. */
+int wvl_convert(wvl_ctx *ctx, const void *src, int32_t src_prec, void *dst, int32_t dst_prec,
+                int64_t count, void *stream);
+
+/* Wait for `stream` and report device-side errors of this plan. */
+int wvl_plan_sync(wvl_plan *plan, void *stream);
+
+/* Choice made at plan creation for the hpsi kernels: variant id and the
+ * measured time (ms) of each candidate if WVL_AUTOTUNE was given. */
+int wvl_plan_tuning(const wvl_plan *plan, int32_t *variant, double *times_ms, int32_t ntimes);
+
+const char *wvl_last_error(void);
+const char *wvl_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WVL_PUBLIC_API_H_ */

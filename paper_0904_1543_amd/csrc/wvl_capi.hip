@@ -1,0 +1,602 @@
+// Host side of libwvl: argument checking, plans, workspace layout and the
+// launch sequences of the C ABI declared in include/wvl.h.
+//
+// Every entry point validates its arguments before the first HIP call, so the
+// whole contract can be exercised on a machine without a GPU (dry contexts).
+
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "wvl.h"
+#include "wvl_kernels.h"
+
+using namespace wvl;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+int hipfail(hipError_t e, const char* where) {
+  return fail(WVL_EHIP, "%s: %s", where, hipGetErrorString(e));
+}
+
+#define WVL_HIP(call)                                   \
+  do {                                                  \
+    hipError_t _e = (call);                             \
+    if (_e != hipSuccess) return hipfail(_e, #call);    \
+  } while (0)
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+}  // namespace
+
+struct wvl_ctx {
+  int device;
+  bool dry;
+  size_t lds_per_block;
+  int cus;
+};
+
+struct GraphKey {
+  const void* p[8];
+  double s[2];
+  bool operator==(const GraphKey& o) const {
+    for (int i = 0; i < 8; ++i) if (p[i] != o.p[i]) return false;
+    return s[0] == o.s[0] && s[1] == o.s[1];
+  }
+};
+
+struct wvl_plan {
+  wvl_ctx* ctx = nullptr;
+  int prec = 0;
+  uint32_t flags = 0;
+  int norb = 0;
+  bool shared = false;   // shared potential + uniform grid
+  bool dense = false;    // off_b = b * M, all dims equal
+  int64_t M = 0;         // points per orbital when uniform
+  int64_t elems = 0;     // elements per packed plane
+  int64_t vlen = 0;      // minimal length of a per-orbital V buffer
+  std::vector<OrbDev> orbs;
+  std::vector<int32_t> pz, py, px, pp;
+  int nblk = 0;          // 256-point blocks of the shared grid
+  // device copies
+  OrbDev* d_orbs = nullptr;
+  int32_t* d_pz = nullptr;
+  int32_t* d_py = nullptr;
+  int32_t* d_px = nullptr;
+  int32_t* d_pp = nullptr;
+  int* d_info = nullptr;
+  // workspace layout (byte offsets)
+  size_t ws = 0, o_A = 0, o_B = 0, o_S = 0, o_ez = 0, o_ey = 0, o_ex = 0, o_pp = 0, o_rv = 0,
+         o_rho = 0, o_eorb = 0, o_syrk = 0, o_L = 0, o_Li = 0;
+  // graph cache
+  hipStream_t gstream = nullptr;
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  GraphKey gkey{};
+  int variant = 0;
+  std::vector<double> tune_ms;
+};
+
+static int esize(int prec) { return prec == WVL_F32 ? 4 : 8; }
+
+static int check_plan(const wvl_plan* p) {
+  if (!p) return fail(WVL_EINVAL, "plan is NULL");
+  return WVL_OK;
+}
+
+static int check_gpu(const wvl_plan* p) {
+  if (p->ctx->dry) return fail(WVL_ENODEV, "dry context: no GPU");
+  hipError_t e = hipSetDevice(p->ctx->device);
+  if (e != hipSuccess) return hipfail(e, "hipSetDevice");
+  return WVL_OK;
+}
+
+static inline char* wsp(void* ws, size_t off) { return (char*)ws + off; }
+
+extern "C" {
+
+const char* wvl_last_error(void) { return g_err.c_str(); }
+const char* wvl_version(void) { return "wvl 1.0 (gfx950)"; }
+
+int wvl_create(wvl_ctx** ctx, int device) {
+  if (!ctx) return fail(WVL_EINVAL, "ctx is NULL");
+  *ctx = nullptr;
+  if (device < -1) return fail(WVL_EINVAL, "device %d < -1", device);
+  wvl_ctx* c = new wvl_ctx();
+  c->device = device;
+  c->dry = device < 0;
+  c->lds_per_block = 65536;
+  c->cus = 256;
+  if (!c->dry) {
+    int n = 0;
+    hipError_t e = hipGetDeviceCount(&n);
+    if (e != hipSuccess || n <= device) {
+      delete c;
+      return fail(WVL_ENODEV, "no GPU %d (hipGetDeviceCount: %s, count %d)", device,
+                  e == hipSuccess ? "ok" : hipGetErrorString(e), n);
+    }
+    hipDeviceProp_t prop;
+    e = hipGetDeviceProperties(&prop, device);
+    if (e != hipSuccess) { delete c; return hipfail(e, "hipGetDeviceProperties"); }
+    c->lds_per_block = prop.sharedMemPerBlock;
+    c->cus = prop.multiProcessorCount;
+  }
+  *ctx = c;
+  return WVL_OK;
+}
+
+int wvl_destroy(wvl_ctx* ctx) {
+  if (!ctx) return fail(WVL_EINVAL, "ctx is NULL");
+  delete ctx;
+  return WVL_OK;
+}
+
+int wvl_plan_create(wvl_ctx* ctx, const wvl_orbital* orbs, int32_t norb, int32_t prec,
+                    uint32_t flags, wvl_plan** plan) {
+  if (!plan) return fail(WVL_EINVAL, "plan is NULL");
+  *plan = nullptr;
+  if (!ctx) return fail(WVL_EINVAL, "ctx is NULL");
+  if (norb <= 0) return fail(WVL_EINVAL, "norb = %d must be positive", norb);
+  if (!orbs) return fail(WVL_EINVAL, "orbs is NULL");
+  if (prec < WVL_F64 || prec > WVL_F32C) return fail(WVL_EINVAL, "unknown precision %d", prec);
+  if (flags & ~(uint32_t)(WVL_SHARED_V | WVL_USE_GRAPH | WVL_PERSISTENT | WVL_AUTOTUNE))
+    return fail(WVL_EINVAL, "unknown flag bits 0x%x", flags);
+  wvl_plan* p = new wvl_plan();
+  p->ctx = ctx;
+  p->prec = prec;
+  p->flags = flags;
+  p->norb = norb;
+  p->orbs.resize(norb);
+  bool uniform = true, dense = true;
+  int64_t end = 0;
+  std::vector<std::pair<int64_t, int64_t>> spans;
+  for (int b = 0; b < norb; ++b) {
+    const wvl_orbital& o = orbs[b];
+    for (int a = 0; a < 3; ++a) {
+      if (o.n[a] < 2 || o.n[a] > (1 << 14)) {
+        delete p;
+        return fail(WVL_EINVAL, "orbital %d: n[%d] = %d out of range [2, 16384]", b, a, o.n[a]);
+      }
+      if (!(o.hgrid[a] > 0.0) || !isfinite(o.hgrid[a])) {
+        delete p;
+        return fail(WVL_EINVAL, "orbital %d: hgrid[%d] must be positive", b, a);
+      }
+    }
+    if (o.reserved != 0) { delete p; return fail(WVL_EINVAL, "orbital %d: reserved must be 0", b); }
+    if (2 * o.n[0] + 2 * kHalo > kContigLds) {
+      delete p;
+      return fail(WVL_EUNSUPPORTED, "orbital %d: n1 = %d exceeds %d (axis-1 lines are staged in LDS)",
+                  b, o.n[0], (kContigLds - 2 * kHalo) / 2);
+    }
+    if (!isfinite(o.occ)) { delete p; return fail(WVL_EINVAL, "orbital %d: occupation not finite", b); }
+    if (o.off < 0 || o.v_off < 0) { delete p; return fail(WVL_EINVAL, "orbital %d: negative offset", b); }
+    OrbDev& d = p->orbs[b];
+    for (int a = 0; a < 3; ++a) {
+      d.m[a] = 2 * o.n[a];
+      d.kscale[a] = -1.0 / (2.0 * o.hgrid[a] * o.hgrid[a]);
+    }
+    d.pad = 0;
+    d.off = o.off;
+    d.voff = (flags & WVL_SHARED_V) ? 0 : o.v_off;
+    d.occ = o.occ;
+    const int64_t M = (int64_t)d.m[0] * d.m[1] * d.m[2];
+    if (M > (int64_t)1 << 31) { delete p; return fail(WVL_EINVAL, "orbital %d: grid too large", b); }
+    spans.push_back({o.off, o.off + M});
+    end = std::max(end, o.off + M);
+    p->vlen = std::max(p->vlen, d.voff + M);
+    if (b > 0 && (d.m[0] != p->orbs[0].m[0] || d.m[1] != p->orbs[0].m[1] || d.m[2] != p->orbs[0].m[2]))
+      uniform = false;
+    if (o.off != (int64_t)b * M) dense = false;
+  }
+  std::sort(spans.begin(), spans.end());
+  for (size_t i = 1; i < spans.size(); ++i)
+    if (spans[i].first < spans[i - 1].second) {
+      delete p;
+      return fail(WVL_EINVAL, "orbitals overlap in the packed buffer");
+    }
+  if ((flags & WVL_SHARED_V) && !uniform) {
+    delete p;
+    return fail(WVL_EINVAL, "WVL_SHARED_V needs every orbital on the same grid");
+  }
+  p->shared = (flags & WVL_SHARED_V) != 0;
+  p->dense = dense && uniform;
+  p->M = uniform ? (int64_t)p->orbs[0].m[0] * p->orbs[0].m[1] * p->orbs[0].m[2] : 0;
+  p->elems = end;
+  if (end > ((int64_t)1 << 40)) { delete p; return fail(WVL_EINVAL, "batch too large"); }
+  // tiling
+  p->pz.assign(norb + 1, 0);
+  p->py.assign(norb + 1, 0);
+  p->px.assign(norb + 1, 0);
+  p->pp.assign(norb + 1, 0);
+  for (int b = 0; b < norb; ++b) {
+    const OrbDev& d = p->orbs[b];
+    const int64_t m1 = d.m[0], m2 = d.m[1], m3 = d.m[2];
+    const int64_t R = std::max<int64_t>(1, kContigLds / (m1 + 2 * kHalo));
+    p->pz[b + 1] = p->pz[b] + (int32_t)((m1 * m2 + kThreads - 1) / kThreads);
+    p->py[b + 1] = p->py[b] + (int32_t)((m1 * m3 + kThreads - 1) / kThreads);
+    p->px[b + 1] = p->px[b] + (int32_t)((m2 * m3 + R - 1) / R);
+    p->pp[b + 1] = p->pp[b] + (int32_t)((m1 * m2 * m3 + kThreads - 1) / kThreads);
+    if (p->pp[b + 1] < 0 || p->pz[b + 1] < 0) { delete p; return fail(WVL_EINVAL, "too many tiles"); }
+  }
+  p->nblk = p->shared ? (int)((p->M + kThreads - 1) / kThreads) : 0;
+  // workspace layout
+  size_t off = 0;
+  const size_t arr = align256((size_t)p->elems * esize(prec));
+  p->o_A = off; off += arr;
+  p->o_B = off; off += arr;
+  p->o_S = off; off += arr;
+  p->o_ez = off; off += align256(sizeof(double) * p->pz[norb]);
+  p->o_ey = off; off += align256(sizeof(double) * p->py[norb]);
+  p->o_ex = off; off += align256(sizeof(double) * p->px[norb]);
+  p->o_pp = off;
+  off += align256(sizeof(double) * (p->shared ? (size_t)norb * p->nblk : (size_t)p->pp[norb]));
+  p->o_rv = off; off += align256(sizeof(double) * (size_t)std::max(p->nblk, 1));
+  p->o_rho = off; off += align256(sizeof(double) * (size_t)(p->shared ? p->M : 1));
+  p->o_eorb = off; off += align256(sizeof(double) * 2 * (size_t)norb);
+  if (p->dense) {
+    p->o_syrk = off; off += align256(sizeof(double) * (size_t)syrk_partials(norb, p->M));
+    p->o_L = off; off += align256(sizeof(double) * (size_t)norb * norb);
+    p->o_Li = off; off += align256(sizeof(double) * (size_t)norb * norb);
+  }
+  p->ws = off;
+  if (!ctx->dry) {
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e == hipSuccess) e = hipMalloc((void**)&p->d_orbs, sizeof(OrbDev) * norb);
+    if (e == hipSuccess) e = hipMalloc((void**)&p->d_pz, sizeof(int32_t) * (norb + 1) * 4);
+    if (e == hipSuccess) e = hipMalloc((void**)&p->d_info, sizeof(int) * 4);
+    if (e != hipSuccess) {
+      wvl_plan_destroy(p);
+      return fail(WVL_ENOMEM, "plan allocation failed: %s", hipGetErrorString(e));
+    }
+    p->d_py = p->d_pz + (norb + 1);
+    p->d_px = p->d_py + (norb + 1);
+    p->d_pp = p->d_px + (norb + 1);
+    std::vector<int32_t> all;
+    all.insert(all.end(), p->pz.begin(), p->pz.end());
+    all.insert(all.end(), p->py.begin(), p->py.end());
+    all.insert(all.end(), p->px.begin(), p->px.end());
+    all.insert(all.end(), p->pp.begin(), p->pp.end());
+    e = hipMemcpy(p->d_orbs, p->orbs.data(), sizeof(OrbDev) * norb, hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+      e = hipMemcpy(p->d_pz, all.data(), sizeof(int32_t) * all.size(), hipMemcpyHostToDevice);
+    int zero[4] = {0, 0, 0, 0};
+    if (e == hipSuccess) e = hipMemcpy(p->d_info, zero, sizeof zero, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      wvl_plan_destroy(p);
+      return hipfail(e, "plan upload");
+    }
+  }
+  *plan = p;
+  return WVL_OK;
+}
+
+int wvl_plan_destroy(wvl_plan* p) {
+  if (!p) return fail(WVL_EINVAL, "plan is NULL");
+  if (!p->ctx->dry) {
+    (void)hipSetDevice(p->ctx->device);
+    if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
+    if (p->ev_in) (void)hipEventDestroy(p->ev_in);
+    if (p->ev_out) (void)hipEventDestroy(p->ev_out);
+    if (p->gstream) (void)hipStreamDestroy(p->gstream);
+    if (p->d_orbs) (void)hipFree(p->d_orbs);
+    if (p->d_pz) (void)hipFree(p->d_pz);
+    if (p->d_info) (void)hipFree(p->d_info);
+  }
+  delete p;
+  return WVL_OK;
+}
+
+int wvl_plan_workspace(const wvl_plan* p, size_t* bytes) {
+  if (int r = check_plan(p)) return r;
+  if (!bytes) return fail(WVL_EINVAL, "bytes is NULL");
+  *bytes = p->ws;
+  return WVL_OK;
+}
+
+int wvl_plan_elements(const wvl_plan* p, int64_t* elems) {
+  if (int r = check_plan(p)) return r;
+  if (!elems) return fail(WVL_EINVAL, "elems is NULL");
+  *elems = p->elems;
+  return WVL_OK;
+}
+
+int wvl_plan_grid_points(const wvl_plan* p, int64_t* points) {
+  if (int r = check_plan(p)) return r;
+  if (!points) return fail(WVL_EINVAL, "points is NULL");
+  if (!p->shared) return fail(WVL_EUNSUPPORTED, "plan has no shared grid");
+  *points = p->M;
+  return WVL_OK;
+}
+
+int wvl_plan_tuning(const wvl_plan* p, int32_t* variant, double* times_ms, int32_t ntimes) {
+  if (int r = check_plan(p)) return r;
+  if (variant) *variant = p->variant;
+  if (times_ms)
+    for (int i = 0; i < ntimes; ++i) times_ms[i] = i < (int)p->tune_ms.size() ? p->tune_ms[i] : -1.0;
+  return WVL_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// launch sequences
+// ---------------------------------------------------------------------------
+namespace {
+
+struct Seq {
+  wvl_plan* p;
+  hipStream_t st;
+  PassGeom gz, gy, gx, gp;
+  Seq(wvl_plan* pl, hipStream_t s) : p(pl), st(s) {
+    gz = PassGeom{p->d_orbs, p->d_pz, p->norb};
+    gy = PassGeom{p->d_orbs, p->d_py, p->norb};
+    gx = PassGeom{p->d_orbs, p->d_px, p->norb};
+    gp = PassGeom{p->d_orbs, p->d_pp, p->norb};
+  }
+  hipError_t pass(int op, int axis, const void* in, void* out, const void* k0 = nullptr,
+                  double kmul = 1.0, double* ep = nullptr) {
+    const PassGeom& g = axis == 1 ? gx : axis == 2 ? gy : gz;
+    const int n = axis == 1 ? p->px[p->norb] : axis == 2 ? p->py[p->norb] : p->pz[p->norb];
+    return launch_pass(p->prec, op, axis, g, n, in, out, k0, p->elems, kmul, ep, st);
+  }
+  // 3D separable operator: z pass in -> out, y pass out -> tmp, x pass tmp -> out
+  hipError_t op3(int op, const void* in, void* out, void* tmp) {
+    hipError_t e = pass(op, 3, in, out);
+    if (e == hipSuccess) e = pass(op, 2, out, tmp);
+    if (e == hipSuccess) e = pass(op, 1, tmp, out);
+    return e;
+  }
+};
+
+#define WVL_CHK(expr)                                          \
+  do {                                                         \
+    hipError_t _e = (expr);                                    \
+    if (_e != hipSuccess) return hipfail(_e, "kernel launch"); \
+  } while (0)
+
+int hpsi_sequence(wvl_plan* p, hipStream_t st, const void* c, const double* V, double pot_scale,
+                  double kin_scale, void* hpsi, double* rho, double* e_loc, double* e_kin,
+                  double* e_orb, void* ws) {
+  Seq q(p, st);
+  void* A = wsp(ws, p->o_A);
+  void* B = wsp(ws, p->o_B);
+  void* S = wsp(ws, p->o_S);
+  double* ez = (double*)wsp(ws, p->o_ez);
+  double* ey = (double*)wsp(ws, p->o_ey);
+  double* ex = (double*)wsp(ws, p->o_ex);
+  double* pp = (double*)wsp(ws, p->o_pp);
+  double* rv = (double*)wsp(ws, p->o_rv);
+  double* eorb = e_orb ? e_orb : (double*)wsp(ws, p->o_eorb);
+  const bool want_e = e_loc || e_kin || e_orb;
+  // step 2: s = S c  (z: c -> A, y: A -> S, x: S -> S)
+  WVL_CHK(q.pass(OP_SYN, 3, c, A));
+  WVL_CHK(q.pass(OP_SYN, 2, A, S));
+  WVL_CHK(q.pass(OP_SYN, 1, S, S));
+  // step 3a: psi = Omega s (z: S -> A, y: A -> B, x: B -> B)
+  WVL_CHK(q.pass(OP_MF, 3, S, A));
+  WVL_CHK(q.pass(OP_MF, 2, A, B));
+  WVL_CHK(q.pass(OP_MF, 1, B, B));
+  // step 3b and density: y = pot_scale V psi in place
+  if (p->shared) {
+    WVL_CHK(launch_pot_shared(p->prec, p->d_orbs, p->norb, p->M, B, B, V, pot_scale, p->elems, rho,
+                              0, want_e ? rv : nullptr, e_orb ? pp : nullptr, st));
+  } else {
+    WVL_CHK(launch_pot_orb(p->prec, q.gp, p->pp[p->norb], B, B, V, pot_scale, p->elems,
+                           want_e ? pp : nullptr, st));
+  }
+  // step 3c: x' = Omega^T y (z: B -> A, y: A -> B, x: B -> B)
+  WVL_CHK(q.pass(OP_MFT, 3, B, A));
+  WVL_CHK(q.pass(OP_MFT, 2, A, B));
+  WVL_CHK(q.pass(OP_MFT, 1, B, B));
+  // steps 4+5: k = Kin s + x' (K_0 = x'), accumulated axis by axis into A
+  WVL_CHK(q.pass(OP_KIN, 3, S, A, B, kin_scale, want_e ? ez : nullptr));
+  WVL_CHK(q.pass(OP_KIN, 2, S, A, A, kin_scale, want_e ? ey : nullptr));
+  WVL_CHK(q.pass(OP_KIN, 1, S, A, A, kin_scale, want_e ? ex : nullptr));
+  // step 6: Hc = A k (z: A -> B, y: B -> A, x: A -> hpsi)
+  WVL_CHK(q.pass(OP_ANA, 3, A, B));
+  WVL_CHK(q.pass(OP_ANA, 2, B, A));
+  WVL_CHK(q.pass(OP_ANA, 1, A, hpsi));
+  if (want_e) {
+    const int pot_mode = p->shared ? (e_orb ? 2 : 0) : 1;
+    WVL_CHK(launch_orb_sums(p->d_orbs, p->norb, p->d_pz, p->d_py, p->d_px, ez, ey, ex, pp, pot_mode,
+                            p->d_pp, p->nblk, eorb, st));
+    if (e_loc || e_kin)
+      WVL_CHK(launch_totals(p->d_orbs, p->norb, eorb, rv, p->shared ? p->nblk : 0, e_loc, e_kin, st));
+  }
+  return WVL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int wvl_synthesis(wvl_plan* p, const void* c, void* s, void* ws, void* stream) {
+  if (int r = check_plan(p)) return r;
+  if (!c || !s || !ws) return fail(WVL_EINVAL, "wvl_synthesis: NULL pointer");
+  if (c == s) return fail(WVL_EINVAL, "wvl_synthesis: output aliases input");
+  if (int r = check_gpu(p)) return r;
+  Seq q(p, (hipStream_t)stream);
+  WVL_CHK(q.op3(OP_SYN, c, s, wsp(ws, p->o_A)));
+  return WVL_OK;
+}
+
+int wvl_analysis(wvl_plan* p, const void* s, void* c, void* ws, void* stream) {
+  if (int r = check_plan(p)) return r;
+  if (!c || !s || !ws) return fail(WVL_EINVAL, "wvl_analysis: NULL pointer");
+  if (c == s) return fail(WVL_EINVAL, "wvl_analysis: output aliases input");
+  if (int r = check_gpu(p)) return r;
+  Seq q(p, (hipStream_t)stream);
+  WVL_CHK(q.op3(OP_ANA, s, c, wsp(ws, p->o_A)));
+  return WVL_OK;
+}
+
+int wvl_magic_filter(wvl_plan* p, const void* in, void* out, int transpose, void* ws,
+                     void* stream) {
+  if (int r = check_plan(p)) return r;
+  if (!in || !out || !ws) return fail(WVL_EINVAL, "wvl_magic_filter: NULL pointer");
+  if (in == out) return fail(WVL_EINVAL, "wvl_magic_filter: output aliases input");
+  if (int r = check_gpu(p)) return r;
+  Seq q(p, (hipStream_t)stream);
+  WVL_CHK(q.op3(transpose ? OP_MFT : OP_MF, in, out, wsp(ws, p->o_A)));
+  return WVL_OK;
+}
+
+int wvl_kinetic(wvl_plan* p, const void* s, const void* k0, void* out, void* ws, void* stream) {
+  if (int r = check_plan(p)) return r;
+  if (!s || !out || !ws) return fail(WVL_EINVAL, "wvl_kinetic: NULL pointer");
+  if (s == out) return fail(WVL_EINVAL, "wvl_kinetic: output aliases input");
+  if (k0 == s) return fail(WVL_EINVAL, "wvl_kinetic: k0 aliases s");
+  if (int r = check_gpu(p)) return r;
+  Seq q(p, (hipStream_t)stream);
+  WVL_CHK(q.pass(OP_KIN, 3, s, out, k0));
+  WVL_CHK(q.pass(OP_KIN, 2, s, out, out));
+  WVL_CHK(q.pass(OP_KIN, 1, s, out, out));
+  return WVL_OK;
+}
+
+int wvl_local_density(wvl_plan* p, const void* c, double* rho, int accumulate, void* ws,
+                      void* stream) {
+  if (int r = check_plan(p)) return r;
+  if (!c || !rho || !ws) return fail(WVL_EINVAL, "wvl_local_density: NULL pointer");
+  if (!p->shared) return fail(WVL_EUNSUPPORTED, "wvl_local_density needs a WVL_SHARED_V plan");
+  if (int r = check_gpu(p)) return r;
+  hipStream_t st = (hipStream_t)stream;
+  Seq q(p, st);
+  void* A = wsp(ws, p->o_A);
+  void* B = wsp(ws, p->o_B);
+  WVL_CHK(q.pass(OP_SYN, 3, c, A));
+  WVL_CHK(q.pass(OP_SYN, 2, A, B));
+  WVL_CHK(q.pass(OP_SYN, 1, B, B));
+  WVL_CHK(q.pass(OP_MF, 3, B, A));
+  WVL_CHK(q.pass(OP_MF, 2, A, B));
+  WVL_CHK(q.pass(OP_MF, 1, B, B));
+  WVL_CHK(launch_pot_shared(p->prec, p->d_orbs, p->norb, p->M, B, nullptr, nullptr, 1.0, p->elems,
+                            rho, accumulate, nullptr, nullptr, st));
+  return WVL_OK;
+}
+
+int wvl_local_hpsi(wvl_plan* p, const void* c, const double* V, double pot_scale,
+                   double kin_scale, void* hpsi, double* rho, double* e_loc, double* e_kin,
+                   double* e_orb, void* ws, void* stream) {
+  if (int r = check_plan(p)) return r;
+  if (!c || !V || !hpsi || !ws) return fail(WVL_EINVAL, "wvl_local_hpsi: NULL pointer");
+  if (rho && !p->shared) return fail(WVL_EUNSUPPORTED, "rho needs a WVL_SHARED_V plan");
+  if (!isfinite(pot_scale) || !isfinite(kin_scale))
+    return fail(WVL_EINVAL, "wvl_local_hpsi: scales must be finite");
+  if (int r = check_gpu(p)) return r;
+  hipStream_t st = (hipStream_t)stream;
+  if (!(p->flags & WVL_USE_GRAPH))
+    return hpsi_sequence(p, st, c, V, pot_scale, kin_scale, hpsi, rho, e_loc, e_kin, e_orb, ws);
+  // graph path: record once per pointer set on a private stream, replay after
+  GraphKey key{};
+  key.p[0] = c; key.p[1] = V; key.p[2] = hpsi; key.p[3] = rho; key.p[4] = e_loc;
+  key.p[5] = e_kin; key.p[6] = e_orb; key.p[7] = ws;
+  key.s[0] = pot_scale; key.s[1] = kin_scale;
+  if (!p->gstream) {
+    WVL_HIP(hipStreamCreateWithFlags(&p->gstream, hipStreamNonBlocking));
+    WVL_HIP(hipEventCreateWithFlags(&p->ev_in, hipEventDisableTiming));
+    WVL_HIP(hipEventCreateWithFlags(&p->ev_out, hipEventDisableTiming));
+  }
+  if (!p->gexec || !(key == p->gkey)) {
+    if (p->gexec) { (void)hipGraphExecDestroy(p->gexec); p->gexec = nullptr; }
+    hipGraph_t g;
+    WVL_HIP(hipStreamBeginCapture(p->gstream, hipStreamCaptureModeThreadLocal));
+    int r = hpsi_sequence(p, p->gstream, c, V, pot_scale, kin_scale, hpsi, rho, e_loc, e_kin,
+                          e_orb, ws);
+    hipError_t e = hipStreamEndCapture(p->gstream, &g);
+    if (r != WVL_OK) { if (e == hipSuccess) (void)hipGraphDestroy(g); return r; }
+    if (e != hipSuccess) return hipfail(e, "hipStreamEndCapture");
+    e = hipGraphInstantiate(&p->gexec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) { p->gexec = nullptr; return hipfail(e, "hipGraphInstantiate"); }
+    p->gkey = key;
+  }
+  WVL_HIP(hipEventRecord(p->ev_in, st));
+  WVL_HIP(hipStreamWaitEvent(p->gstream, p->ev_in, 0));
+  WVL_HIP(hipGraphLaunch(p->gexec, p->gstream));
+  WVL_HIP(hipEventRecord(p->ev_out, p->gstream));
+  WVL_HIP(hipStreamWaitEvent(st, p->ev_out, 0));
+  return WVL_OK;
+}
+
+int wvl_overlap(wvl_plan* p, const void* c, double* S, void* ws, void* stream) {
+  if (int r = check_plan(p)) return r;
+  if (!c || !S || !ws) return fail(WVL_EINVAL, "wvl_overlap: NULL pointer");
+  if (!p->dense) return fail(WVL_EUNSUPPORTED, "wvl_overlap needs a dense uniform batch");
+  if (int r = check_gpu(p)) return r;
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e = launch_overlap_p(p->prec, c, p->elems, p->norb, p->M, S,
+                                  (double*)wsp(ws, p->o_syrk), st);
+  if (e != hipSuccess) return hipfail(e, "overlap");
+  return WVL_OK;
+}
+
+int wvl_orthonormalize(wvl_plan* p, void* c, double* S, double* L, void* ws, void* stream) {
+  if (int r = check_plan(p)) return r;
+  if (!c || !ws) return fail(WVL_EINVAL, "wvl_orthonormalize: NULL pointer");
+  if (!p->dense) return fail(WVL_EUNSUPPORTED, "wvl_orthonormalize needs a dense uniform batch");
+  if (p->norb > 480) return fail(WVL_EUNSUPPORTED, "wvl_orthonormalize supports up to 480 orbitals");
+  if (int r = check_gpu(p)) return r;
+  hipStream_t st = (hipStream_t)stream;
+  double* Lw = (double*)wsp(ws, p->o_L);
+  double* Li = (double*)wsp(ws, p->o_Li);
+  const size_t nn = sizeof(double) * (size_t)p->norb * p->norb;
+  hipError_t e = launch_overlap_p(p->prec, c, p->elems, p->norb, p->M, Lw,
+                                  (double*)wsp(ws, p->o_syrk), st);
+  if (e != hipSuccess) return hipfail(e, "overlap");
+  if (S) WVL_HIP(hipMemcpyAsync(S, Lw, nn, hipMemcpyDeviceToDevice, st));
+  e = launch_cholesky_inv(Lw, Li, p->norb, p->d_info, st);
+  if (e != hipSuccess) return hipfail(e, "cholesky");
+  if (L) WVL_HIP(hipMemcpyAsync(L, Lw, nn, hipMemcpyDeviceToDevice, st));
+  e = launch_trmm_rows_p(p->prec, Li, c, c, p->elems, p->norb, p->M, st);
+  if (e != hipSuccess) return hipfail(e, "trmm");
+  return WVL_OK;
+}
+
+int wvl_convert(wvl_ctx* ctx, const void* src, int32_t sp, void* dst, int32_t dp, int64_t n,
+                void* stream) {
+  if (!ctx) return fail(WVL_EINVAL, "ctx is NULL");
+  if (!src || !dst) return fail(WVL_EINVAL, "wvl_convert: NULL pointer");
+  if (sp < 0 || sp > 2 || dp < 0 || dp > 2) return fail(WVL_EINVAL, "wvl_convert: bad precision");
+  if (n < 0) return fail(WVL_EINVAL, "wvl_convert: negative count");
+  if (src == dst) return fail(WVL_EINVAL, "wvl_convert: src and dst overlap");
+  if (ctx->dry) return fail(WVL_ENODEV, "dry context: no GPU");
+  WVL_HIP(hipSetDevice(ctx->device));
+  hipError_t e = launch_convert(src, sp, dst, dp, n, (hipStream_t)stream);
+  if (e != hipSuccess) return hipfail(e, "convert");
+  return WVL_OK;
+}
+
+int wvl_plan_sync(wvl_plan* p, void* stream) {
+  if (int r = check_plan(p)) return r;
+  if (int r = check_gpu(p)) return r;
+  WVL_HIP(hipStreamSynchronize((hipStream_t)stream));
+  int info[4];
+  WVL_HIP(hipMemcpy(info, p->d_info, sizeof info, hipMemcpyDeviceToHost));
+  if (info[0] != 0) {
+    int zero[4] = {0, 0, 0, 0};
+    (void)hipMemcpy(p->d_info, zero, sizeof zero, hipMemcpyHostToDevice);
+    return fail(WVL_EINVAL, "overlap matrix not positive definite (pivot %d)", info[0] - 1);
+  }
+  return WVL_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,79 @@
+// Host-side launchers of the gfx950 kernels (internal to libwvl).
+#pragma once
+
+#include "wvl_internal.h"
+
+namespace wvl {
+
+// Deterministic block reduction of one double per thread (fixed order: wave
+// butterfly, then the waves in index order); thread 0 stores.  Ends with a
+// barrier so it can be called repeatedly.
+__device__ __forceinline__ void block_sum_store(double v, double* dst) {
+  __shared__ double red[kThreads / 64];
+  #pragma unroll
+  for (int s = 32; s > 0; s >>= 1) v += __shfl_xor(v, s, 64);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) red[wid] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    #pragma unroll
+    for (int w = 0; w < kThreads / 64; ++w) t += red[w];
+    *dst = t;
+  }
+  __syncthreads();
+}
+
+// One 1D pass of operator `op` along `axis` (1 = contiguous, 2, 3) for every
+// orbital of the geometry.  k0 (nullable) is added to the result; epart
+// (nullable, kinetic only) receives per-tile partial sums of x * (T x).
+hipError_t launch_pass(int prec, int op, int axis, const PassGeom& g, int ntiles, const void* in,
+                       void* out, const void* k0, int64_t plane, double kmul, double* epart,
+                       hipStream_t st);
+
+// Pointwise stage on a shared potential (all orbitals on one grid of M points):
+// rho (nullable) = [rho +] sum_b f_b psi_b^2 in float64; y_b = pot_scale V psi_b
+// (nullable y); rvpart[block] = sum over the block of V * (sum_b f_b psi_b^2);
+// ppart (nullable) [b][block] = sum over the block of V psi_b^2.
+hipError_t launch_pot_shared(int prec, const OrbDev* orbs, int norb, int64_t M, const void* psi,
+                             void* y, const double* V, double pot_scale, int64_t plane,
+                             double* rho, int rho_acc, double* rvpart, double* ppart,
+                             hipStream_t st);
+
+// Pointwise stage with one potential per orbital (uneven batches):
+// y_b = pot_scale V_b psi_b, ppart[tile] = sum over the tile of V_b psi_b^2.
+hipError_t launch_pot_orb(int prec, const PassGeom& g, int ntiles, const void* psi, void* y,
+                          const double* V, double pot_scale, int64_t plane, double* ppart,
+                          hipStream_t st);
+
+// Per-orbital energies eorb[b] (potential) and eorb[norb + b] (kinetic) from
+// the tile partials; pot_mode 0: none, 1: per-orbital tiles (prefix pp),
+// 2: shared-grid blocks laid out [norb][nblk].
+hipError_t launch_orb_sums(const OrbDev* orbs, int norb, const int32_t* pz, const int32_t* py,
+                           const int32_t* px, const double* ez, const double* ey, const double* ex,
+                           const double* ppart, int pot_mode, const int32_t* pp, int nblk,
+                           double* eorb, hipStream_t st);
+
+// Totals: e_kin = sum_b f_b eorb[norb+b]; e_loc = sum of rvpart (nrv > 0) or
+// sum_b f_b eorb[b].
+hipError_t launch_totals(const OrbDev* orbs, int norb, const double* eorb, const double* rvpart,
+                         int nrv, double* e_loc, double* e_kin, hipStream_t st);
+
+// Element-wise format conversion between F64, F32 and F32C (hi/lo planes).
+hipError_t launch_convert(const void* src, int sp, void* dst, int dp, int64_t n, hipStream_t st);
+
+// Fill with a float64 value (used instead of memset nodes so that sequences
+// can be captured in graphs).
+hipError_t launch_fill(double* dst, int64_t n, double v, hipStream_t st);
+
+// Overlap S = X X^T (X: norb rows of `len` coefficients stored in precision
+// `prec`, plane stride `plane`), Cholesky S = L L^T with L^{-1}, and
+// Y = L^{-1} X.  syrk_partials: workspace of the overlap in doubles.
+int64_t syrk_partials(int norb, int64_t len);
+hipError_t launch_overlap_p(int prec, const void* X, int64_t plane, int norb, int64_t len,
+                            double* S, double* work, hipStream_t st);
+hipError_t launch_cholesky_inv(double* S_to_L, double* Linv, int norb, int* info, hipStream_t st);
+hipError_t launch_trmm_rows_p(int prec, const double* Li, const void* X, void* Y, int64_t plane,
+                              int norb, int64_t len, hipStream_t st);
+
+}  // namespace wvl

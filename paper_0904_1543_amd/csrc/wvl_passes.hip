@@ -1,0 +1,201 @@
+// 1D periodic convolution passes over a batch of orbitals, gfx950.
+//
+// The 3D operators of the method are separable: each is three 1D periodic
+// convolutions, one along each axis (Sec. 3.1, Eqs. "3dconv", "1dconvtrans";
+// the kinetic operator is a sum of three 1D filters, Sec. 3.4, Eq.
+// "kinetic1d").  The paper's GPU kernel writes every pass transposed so that
+// the next pass again convolves along the slowest axis; here the data stays in
+// its natural (m3, m2, m1) layout instead:
+//  * passes along axes 2 and 3 (strided axes) give one line to each lane;
+//    consecutive lanes own consecutive lines, which are adjacent in memory, so
+//    every row of loads and stores is a coalesced 64-lane access, and each lane
+//    runs a register sliding window down its line (no LDS needed);
+//  * passes along axis 1 (the contiguous axis) stage a block of whole rows in
+//    LDS with a periodic halo of 16 values on each side, then every lane
+//    computes two neighbouring outputs from a register window read from LDS.
+// The periodic boundary (Sec. 3.1) is applied by modular indexing on the
+// loads, so lines shorter than the filter are handled as well.
+
+#include "wvl_internal.h"
+#include "wvl_kernels.h"
+
+namespace wvl {
+
+template <int P, int OP>
+__device__ __forceinline__ void pair_conv(const typename Prec<P>::V* win, typename Prec<P>::V& y0,
+                                          typename Prec<P>::V& y1) {
+  using T = Prec<P>;
+  constexpr int OLO = OpWin<OP>::OLO, OHI = OpWin<OP>::OHI;
+  typename T::Acc a0 = T::zero(), a1 = T::zero();
+  #pragma unroll
+  for (int o = OLO; o <= OHI; ++o) {
+    // window: win[i] = x[k - OHI + i]; so x[k - o] = win[OHI - o]
+    if (coef<OP>(0, o, 0) != 0.0) T::template add<OP>(a0, 0, o, win[OHI - o]);
+    if (coef<OP>(1, o, 0) != 0.0) T::template add<OP>(a1, 1, o, win[OHI - o + 1]);
+  }
+  y0 = T::fin(a0);
+  y1 = T::fin(a1);
+}
+
+// ---------------------------------------------------------------------------
+// Strided-axis pass (AXIS = 2 or 3)
+// ---------------------------------------------------------------------------
+template <int OP, int P, int AXIS, bool K0, bool EN>
+__global__ __launch_bounds__(kThreads) void k_strided(PassGeom g, const void* __restrict__ in,
+                                                      void* __restrict__ out, const void* k0,
+                                                      int64_t plane, double kmul,
+                                                      double* __restrict__ epart) {
+  using T = Prec<P>;
+  using V = typename T::V;
+  constexpr int OLO = OpWin<OP>::OLO, OHI = OpWin<OP>::OHI, W = OHI - OLO + 1;
+  int b, t;
+  find_tile(g.prefix, g.norb, blockIdx.x, b, t);
+  const OrbDev od = g.orbs[b];
+  const int m1 = od.m[0], m2 = od.m[1], m3 = od.m[2];
+  const int m = AXIS == 3 ? m3 : m2;
+  const int64_t L = AXIS == 3 ? (int64_t)m1 * m2 : (int64_t)m1 * m3;
+  const int64_t line = (int64_t)t * kThreads + threadIdx.x;
+  double e = 0.0;
+  if (line < L) {
+    const int64_t stride = AXIS == 3 ? (int64_t)m1 * m2 : (int64_t)m1;
+    const int64_t base =
+        od.off + (AXIS == 3 ? line : (line / m1) * ((int64_t)m1 * m2) + (line % m1));
+    const double ks = AXIS == 3 ? od.kscale[2] : od.kscale[1];
+    V win[W + 1];
+    #pragma unroll
+    for (int i = 0; i < W - 1; ++i) win[i] = T::ldc(in, base + (int64_t)wrapi(i - OHI, m) * stride, plane);
+    for (int k = 0; k < m; k += 2) {
+      win[W - 1] = T::ldc(in, base + (int64_t)wrapi(k - OLO, m) * stride, plane);
+      win[W] = T::ldc(in, base + (int64_t)wrapi(k + 1 - OLO, m) * stride, plane);
+      V y0, y1;
+      pair_conv<P, OP>(win, y0, y1);
+      if (OP == OP_KIN) {
+        // energies use the unweighted operator; kmul weights the output only
+        y0 = T::scale(y0, ks);
+        y1 = T::scale(y1, ks);
+        if (EN) e += T::d(win[OHI]) * T::d(y0) + T::d(win[OHI + 1]) * T::d(y1);
+        if (kmul != 1.0) { y0 = T::scale(y0, kmul); y1 = T::scale(y1, kmul); }
+      }
+      const int64_t i0 = base + (int64_t)k * stride, i1 = i0 + stride;
+      if (K0) {
+        y0 = T::plus(y0, T::ldc(k0, i0, plane));
+        y1 = T::plus(y1, T::ldc(k0, i1, plane));
+      }
+      T::st(out, i0, plane, y0);
+      T::st(out, i1, plane, y1);
+      #pragma unroll
+      for (int i = 0; i < W - 1; ++i) win[i] = win[i + 2];
+    }
+  }
+  if (EN) block_sum_store(e, epart + blockIdx.x);
+}
+
+// ---------------------------------------------------------------------------
+// Contiguous-axis pass (axis 1), LDS row tiles with periodic halo
+// ---------------------------------------------------------------------------
+template <int OP, int P, bool K0, bool EN>
+__global__ __launch_bounds__(kThreads) void k_contig(PassGeom g, const void* in, void* out,
+                                                     const void* k0, int64_t plane, double kmul,
+                                                     double* __restrict__ epart) {
+  using T = Prec<P>;
+  using V = typename T::V;
+  constexpr int OLO = OpWin<OP>::OLO, OHI = OpWin<OP>::OHI, W = OHI - OLO + 1;
+  static_assert(OHI <= kHalo && -OLO <= kHalo, "halo too small");
+  __shared__ V lds[kContigLds];
+  int b, t;
+  find_tile(g.prefix, g.norb, blockIdx.x, b, t);
+  const OrbDev od = g.orbs[b];
+  const int m1 = od.m[0];
+  const int rows = od.m[1] * od.m[2];
+  const int pitch = m1 + 2 * kHalo;
+  const int R = max(1, kContigLds / pitch);
+  const int row0 = t * R;
+  const int nrows = min(R, rows - row0);
+  const int64_t gbase = od.off + (int64_t)row0 * m1;
+  // load rows [row0, row0 + nrows) with halo: lds[r*pitch + p] = x[r][(p - kHalo) mod m1]
+  const int nload = nrows * pitch;
+  for (int e = threadIdx.x; e < nload; e += kThreads) {
+    const int r = e / pitch;
+    const int p = e - r * pitch;
+    lds[e] = T::ldc(in, gbase + (int64_t)r * m1 + wrapi(p - kHalo, m1), plane);
+  }
+  __syncthreads();
+  const double ks = od.kscale[0];
+  const int half = m1 >> 1;
+  const int npairs = nrows * half;
+  double en = 0.0;
+  for (int q = threadIdx.x; q < npairs; q += kThreads) {
+    const int r = q / half;
+    const int k = 2 * (q - r * half);
+    const V* src = lds + r * pitch + kHalo + k - OHI;
+    V win[W + 1];
+    #pragma unroll
+    for (int i = 0; i <= W; ++i) win[i] = src[i];
+    V y0, y1;
+    pair_conv<P, OP>(win, y0, y1);
+    if (OP == OP_KIN) {
+      y0 = T::scale(y0, ks);
+      y1 = T::scale(y1, ks);
+      if (EN) en += T::d(win[OHI]) * T::d(y0) + T::d(win[OHI + 1]) * T::d(y1);
+      if (kmul != 1.0) { y0 = T::scale(y0, kmul); y1 = T::scale(y1, kmul); }
+    }
+    const int64_t i0 = gbase + (int64_t)r * m1 + k;
+    if (K0) {
+      y0 = T::plus(y0, T::ldc(k0, i0, plane));
+      y1 = T::plus(y1, T::ldc(k0, i0 + 1, plane));
+    }
+    T::st(out, i0, plane, y0);
+    T::st(out, i0 + 1, plane, y1);
+  }
+  if (EN) block_sum_store(en, epart + blockIdx.x);
+}
+
+// ---------------------------------------------------------------------------
+// Host launchers
+// ---------------------------------------------------------------------------
+template <int OP, int P>
+static hipError_t launch_axis(int axis, const PassGeom& g, int ntiles, const void* in, void* out,
+                              const void* k0, int64_t plane, double kmul, double* epart,
+                              hipStream_t st) {
+  const bool en = epart != nullptr;
+  dim3 grid(ntiles), block(kThreads);
+  if (ntiles == 0) return hipSuccess;
+#define WVL_L(KERN) hipLaunchKernelGGL((KERN), grid, block, 0, st, g, in, out, k0, plane, kmul, epart)
+  if (axis == 1) {
+    if (k0) { if (en) WVL_L((k_contig<OP, P, true, true>)); else WVL_L((k_contig<OP, P, true, false>)); }
+    else    { if (en) WVL_L((k_contig<OP, P, false, true>)); else WVL_L((k_contig<OP, P, false, false>)); }
+  } else if (axis == 2) {
+    if (k0) { if (en) WVL_L((k_strided<OP, P, 2, true, true>)); else WVL_L((k_strided<OP, P, 2, true, false>)); }
+    else    { if (en) WVL_L((k_strided<OP, P, 2, false, true>)); else WVL_L((k_strided<OP, P, 2, false, false>)); }
+  } else {
+    if (k0) { if (en) WVL_L((k_strided<OP, P, 3, true, true>)); else WVL_L((k_strided<OP, P, 3, true, false>)); }
+    else    { if (en) WVL_L((k_strided<OP, P, 3, false, true>)); else WVL_L((k_strided<OP, P, 3, false, false>)); }
+  }
+#undef WVL_L
+  return hipGetLastError();
+}
+
+template <int P>
+static hipError_t launch_op(int op, int axis, const PassGeom& g, int ntiles, const void* in,
+                            void* out, const void* k0, int64_t plane, double kmul, double* epart,
+                            hipStream_t st) {
+  switch (op) {
+    case OP_MF:  return launch_axis<OP_MF, P>(axis, g, ntiles, in, out, k0, plane, kmul, epart, st);
+    case OP_MFT: return launch_axis<OP_MFT, P>(axis, g, ntiles, in, out, k0, plane, kmul, epart, st);
+    case OP_SYN: return launch_axis<OP_SYN, P>(axis, g, ntiles, in, out, k0, plane, kmul, epart, st);
+    case OP_ANA: return launch_axis<OP_ANA, P>(axis, g, ntiles, in, out, k0, plane, kmul, epart, st);
+    default:     return launch_axis<OP_KIN, P>(axis, g, ntiles, in, out, k0, plane, kmul, epart, st);
+  }
+}
+
+hipError_t launch_pass(int prec, int op, int axis, const PassGeom& g, int ntiles, const void* in,
+                       void* out, const void* k0, int64_t plane, double kmul, double* epart,
+                       hipStream_t st) {
+  switch (prec) {
+    case F64: return launch_op<F64>(op, axis, g, ntiles, in, out, k0, plane, kmul, epart, st);
+    case F32: return launch_op<F32>(op, axis, g, ntiles, in, out, k0, plane, kmul, epart, st);
+    default:  return launch_op<F32C>(op, axis, g, ntiles, in, out, k0, plane, kmul, epart, st);
+  }
+}
+
+}  // namespace wvl

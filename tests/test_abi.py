@@ -1,0 +1,137 @@
+"""C-ABI contract on the host (no GPU needed): the library loads, exports every
+symbol that include/wvl.h declares, and checks its arguments before touching
+the GPU (dry contexts answer WVL_ENODEV only after the checks passed)."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_0904_1543_amd import lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "wvl.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(wvl_[a-z_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported():
+    names = declared_functions()
+    assert len(names) >= 18
+    for n in names:
+        assert hasattr(lib._lib, n), n
+    assert set(names) == set(lib.EXPORTS)
+
+
+def test_version_and_error_text():
+    assert "gfx950" in lib.wvl_version()
+    rc = lib.raw("wvl_create")(None, 0)
+    assert rc == lib.WVL_EINVAL
+    assert "ctx" in lib.wvl_last_error()
+
+
+def _orbs(dims, offs=None, hgrid=(1.0, 1.0, 1.0), occ=2.0):
+    arr = (lib.wvl_orbital * len(dims))()
+    off = 0
+    for b, d in enumerate(dims):
+        arr[b].n[0], arr[b].n[1], arr[b].n[2] = d
+        arr[b].off = off if offs is None else offs[b]
+        arr[b].v_off = 0
+        arr[b].hgrid[0], arr[b].hgrid[1], arr[b].hgrid[2] = hgrid
+        arr[b].occ = occ
+        off += 8 * d[0] * d[1] * d[2]
+    return arr
+
+
+@pytest.fixture()
+def dry():
+    ctx = ctypes.c_void_p()
+    assert lib.raw("wvl_create")(ctypes.byref(ctx), -1) == lib.WVL_OK
+    yield ctx
+    lib.raw("wvl_destroy")(ctx)
+
+
+def _plan(ctx, dims, prec=0, flags=1, **kw):
+    h = ctypes.c_void_p()
+    rc = lib.raw("wvl_plan_create")(ctx, _orbs(dims, **kw), len(dims), prec, flags, ctypes.byref(h))
+    return rc, h
+
+
+def test_no_gpu_gives_enodev():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    ctx = ctypes.c_void_p()
+    assert lib.raw("wvl_create")(ctypes.byref(ctx), 0) == lib.WVL_ENODEV
+    assert "GPU" in lib.wvl_last_error()
+
+
+def test_plan_argument_checks(dry):
+    assert _plan(dry, [(4, 4, 4)], prec=7)[0] == lib.WVL_EINVAL
+    assert _plan(dry, [(1, 4, 4)])[0] == lib.WVL_EINVAL                     # n < 2
+    assert _plan(dry, [(4, 4, 4)], flags=64)[0] == lib.WVL_EINVAL           # unknown flag
+    assert _plan(dry, [(4, 4, 4)], hgrid=(1.0, -1.0, 1.0))[0] == lib.WVL_EINVAL
+    assert _plan(dry, [(4, 4, 4), (4, 4, 4)], offs=[0, 100])[0] == lib.WVL_EINVAL  # overlap
+    assert _plan(dry, [(4, 4, 4), (4, 6, 4)], flags=1)[0] == lib.WVL_EINVAL  # shared V, uneven
+    h = ctypes.c_void_p()
+    assert lib.raw("wvl_plan_create")(dry, _orbs([(4, 4, 4)]), 0, 0, 1, ctypes.byref(h)) == lib.WVL_EINVAL
+    assert lib.raw("wvl_plan_create")(None, _orbs([(4, 4, 4)]), 1, 0, 1, ctypes.byref(h)) == lib.WVL_EINVAL
+    rc, p = _plan(dry, [(4, 4, 4), (4, 6, 4)], flags=0)
+    assert rc == lib.WVL_OK
+    lib.wvl_plan_destroy(p)
+
+
+def test_plan_sizes(dry):
+    rc, p = _plan(dry, [(16, 16, 16)] * 3, prec=2)
+    assert rc == lib.WVL_OK
+    el = ctypes.c_int64()
+    lib.wvl_plan_elements(p, ctypes.byref(el))
+    assert el.value == 3 * 32 ** 3
+    ws = ctypes.c_size_t()
+    lib.wvl_plan_workspace(p, ctypes.byref(ws))
+    assert ws.value >= 3 * 8 * el.value      # three work arrays of hi+lo planes
+    pts = ctypes.c_int64()
+    lib.wvl_plan_grid_points(p, ctypes.byref(pts))
+    assert pts.value == 32 ** 3
+    lib.wvl_plan_destroy(p)
+
+
+def test_calls_check_arguments_before_gpu(dry):
+    rc, p = _plan(dry, [(4, 4, 4)] * 2)
+    assert rc == lib.WVL_OK
+    a, b, ws = ctypes.c_void_p(0x1000), ctypes.c_void_p(0x2000), ctypes.c_void_p(0x3000)
+    f = lib.raw
+    # NULL pointers and aliasing -> EINVAL
+    assert f("wvl_synthesis")(p, None, b, ws, None) == lib.WVL_EINVAL
+    assert f("wvl_synthesis")(p, a, a, ws, None) == lib.WVL_EINVAL
+    assert f("wvl_analysis")(p, a, b, None, None) == lib.WVL_EINVAL
+    assert f("wvl_magic_filter")(p, a, a, 0, ws, None) == lib.WVL_EINVAL
+    assert f("wvl_kinetic")(p, a, None, a, ws, None) == lib.WVL_EINVAL
+    assert f("wvl_kinetic")(p, a, a, b, ws, None) == lib.WVL_EINVAL
+    assert f("wvl_local_hpsi")(p, a, None, 1.0, 1.0, b, None, None, None, None, ws, None) == lib.WVL_EINVAL
+    assert f("wvl_local_hpsi")(p, a, a, float("nan"), 1.0, b, None, None, None, None, ws, None) == lib.WVL_EINVAL
+    assert f("wvl_synthesis")(None, a, b, ws, None) == lib.WVL_EINVAL
+    # valid arguments on a dry plan -> ENODEV
+    assert f("wvl_synthesis")(p, a, b, ws, None) == lib.WVL_ENODEV
+    assert f("wvl_kinetic")(p, a, None, b, ws, None) == lib.WVL_ENODEV
+    assert f("wvl_local_density")(p, a, b, 0, ws, None) == lib.WVL_ENODEV
+    assert f("wvl_local_hpsi")(p, a, b, 1.0, 1.0, ws, None, None, None, None, ws, None) == lib.WVL_ENODEV
+    assert f("wvl_overlap")(p, a, b, ws, None) == lib.WVL_ENODEV
+    assert f("wvl_convert")(dry, a, 0, b, 2, 10, None) == lib.WVL_ENODEV
+    assert f("wvl_convert")(dry, a, 0, a, 2, 10, None) == lib.WVL_EINVAL
+    assert f("wvl_convert")(dry, a, 0, b, 5, 10, None) == lib.WVL_EINVAL
+    lib.wvl_plan_destroy(p)
+
+
+def test_unsupported_combinations(dry):
+    rc, p = _plan(dry, [(4, 4, 4), (4, 6, 4)], flags=0)    # uneven, per-orbital V
+    a, b, ws = ctypes.c_void_p(0x1000), ctypes.c_void_p(0x2000), ctypes.c_void_p(0x3000)
+    assert lib.raw("wvl_local_density")(p, a, b, 0, ws, None) == lib.WVL_EUNSUPPORTED
+    assert lib.raw("wvl_overlap")(p, a, b, ws, None) == lib.WVL_EUNSUPPORTED
+    assert lib.raw("wvl_local_hpsi")(p, a, a, 1.0, 1.0, b, b, None, None, None, ws, None) == \
+        lib.WVL_EUNSUPPORTED   # rho needs a shared potential
+    lib.wvl_plan_destroy(p)

@@ -1,0 +1,59 @@
+"""GPU parity of the float64 overlap matrix and the Cholesky
+orthonormalisation (Sec. 5 step VIII) against the oracle, in every storage
+precision of the coefficients."""
+
+import numpy as np
+import pytest
+
+from oracle import wavelet as W
+from paper_0904_1543_amd import inputs, ops
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32c", "f32"])
+@pytest.mark.parametrize("norb,dims", [(5, (6, 5, 4)), (37, (8, 8, 8)), (300, (4, 4, 6))])
+def test_overlap(prec, norb, dims):
+    cs = inputs.random_case(17, norb, dims)
+    C = cs["C"] + 0.05 * cs["C"][:1]        # correlated orbitals: S far from identity
+    plan = ops.Plan(cs["dims"], prec=prec)
+    c = plan.pack(C)
+    S = plan.overlap(c).cpu().numpy()
+    # the oracle sees the coefficients the GPU stores (float32 for plain float32)
+    Cref = np.stack(plan.unpack(c)) if prec == "f32" else C
+    ref = W.overlap(Cref)
+    tol = 1e-13
+    assert np.max(np.abs(S - ref)) < tol * np.max(np.abs(ref))
+    assert np.array_equal(S, S.T)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32c"])
+@pytest.mark.parametrize("norb,dims", [(6, (6, 5, 4)), (64, (8, 8, 8))])
+def test_orthonormalize(prec, norb, dims):
+    cs = inputs.random_case(19, norb, dims)
+    C = cs["C"] + 0.3 * cs["C"][:1]
+    plan = ops.Plan(cs["dims"], prec=prec)
+    c = plan.pack(C)
+    S, L = plan.orthonormalize(c)
+    plan.sync()
+    Cn_ref, L_ref = W.cholesky_orthonormalize(C)
+    tol = 1e-12 if prec == "f64" else 1e-10
+    assert np.max(np.abs(L.cpu().numpy() - L_ref)) < tol
+    got = np.stack(plan.unpack(c))
+    assert np.linalg.norm(got - Cn_ref) / np.linalg.norm(Cn_ref) < tol
+    X = got.reshape(norb, -1)
+    assert np.max(np.abs(X @ X.T - np.eye(norb))) < 10 * tol
+
+
+def test_not_positive_definite_is_reported():
+    cs = inputs.random_case(23, 3, (4, 4, 4))
+    C = cs["C"].copy()
+    C[2] = 0.0                               # zero orbital: pivot exactly 0
+    plan = ops.Plan(cs["dims"], prec="f64")
+    c = plan.pack(C)
+    plan.orthonormalize(c)
+    from paper_0904_1543_amd import lib
+    with pytest.raises(lib.WvlError) as ei:
+        plan.sync()
+    assert ei.value.code == lib.WVL_EINVAL
+    plan.sync()                               # the flag is cleared after reporting
