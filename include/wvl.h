@@ -162,6 +162,18 @@ int wvl_plan_sync(wvl_plan *plan, void *stream);
  * measured time (ms) of each candidate if WVL_AUTOTUNE was given. */
 int wvl_plan_tuning(const wvl_plan *plan, int32_t *variant, double *times_ms, int32_t ntimes);
 
+/* Launch profiling: with capacity > 0, every kernel launch of the following
+ * calls on this plan (eager mode; graph replays are not split) is bracketed
+ * by a pair of hipEvents recorded on the call's stream, up to `capacity`
+ * launches; capacity = 0 disables.  wvl_plan_profile_read() waits for the
+ * recorded events, returns up to `max` (stage id, milliseconds) pairs in
+ * launch order, their number in *count, and clears the records.
+ * wvl_stage_name() names a stage id ("kin_z", "potential", "overlap", ...). */
+int wvl_plan_profile(wvl_plan *plan, int32_t capacity);
+int wvl_plan_profile_read(wvl_plan *plan, int32_t *stage, double *ms, int32_t max,
+                          int32_t *count);
+const char *wvl_stage_name(int32_t stage);
+
 const char *wvl_last_error(void);
 const char *wvl_version(void);
 

@@ -93,7 +93,41 @@ struct wvl_plan {
   GraphKey gkey{};
   int variant = 0;
   std::vector<double> tune_ms;
+  // launch profiling (hipEvent pairs around every launch of a call)
+  struct Rec { int stage; hipEvent_t a, b; };
+  std::vector<Rec> prof;
+  int prof_cap = 0, prof_used = 0;
+  bool capturing = false;
 };
+
+// Stage ids for profiling: 1D passes are op * 3 + (axis - 1); then:
+enum { ST_POT = 15, ST_ENERGY = 16, ST_OVERLAP = 17, ST_CHOL = 18, ST_TRMM = 19, ST_NSTAGE = 20 };
+static const char* kStageNames[ST_NSTAGE] = {
+    "mf_x", "mf_y", "mf_z", "mft_x", "mft_y", "mft_z", "syn_x", "syn_y", "syn_z",
+    "ana_x", "ana_y", "ana_z", "kin_x", "kin_y", "kin_z", "potential", "energies",
+    "overlap", "cholesky", "trmm"};
+
+namespace {
+struct Mark {
+  wvl_plan* p;
+  hipStream_t st;
+  int slot = -1;
+  Mark(wvl_plan* pl, hipStream_t s, int stage) : p(pl), st(s) {
+    if (p->prof_cap <= 0 || p->capturing || p->prof_used >= p->prof_cap) return;
+    if ((int)p->prof.size() <= p->prof_used) {
+      wvl_plan::Rec r{stage, nullptr, nullptr};
+      if (hipEventCreate(&r.a) != hipSuccess || hipEventCreate(&r.b) != hipSuccess) return;
+      p->prof.push_back(r);
+    }
+    slot = p->prof_used++;
+    p->prof[slot].stage = stage;
+    (void)hipEventRecord(p->prof[slot].a, st);
+  }
+  ~Mark() {
+    if (slot >= 0) (void)hipEventRecord(p->prof[slot].b, st);
+  }
+};
+}  // namespace
 
 static int esize(int prec) { return prec == WVL_F32 ? 4 : 8; }
 
@@ -293,6 +327,10 @@ int wvl_plan_destroy(wvl_plan* p) {
   if (!p->ctx->dry) {
     (void)hipSetDevice(p->ctx->device);
     if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
+    for (auto& r : p->prof) {
+      (void)hipEventDestroy(r.a);
+      (void)hipEventDestroy(r.b);
+    }
     if (p->ev_in) (void)hipEventDestroy(p->ev_in);
     if (p->ev_out) (void)hipEventDestroy(p->ev_out);
     if (p->gstream) (void)hipStreamDestroy(p->gstream);
@@ -353,6 +391,7 @@ struct Seq {
   }
   hipError_t pass(int op, int axis, const void* in, void* out, const void* k0 = nullptr,
                   double kmul = 1.0, double* ep = nullptr) {
+    Mark mk(p, st, op * 3 + axis - 1);
     const PassGeom& g = axis == 1 ? gx : axis == 2 ? gy : gz;
     const int n = axis == 1 ? p->px[p->norb] : axis == 2 ? p->py[p->norb] : p->pz[p->norb];
     return launch_pass(p->prec, op, axis, g, n, in, out, k0, p->elems, kmul, ep, st);
@@ -395,12 +434,15 @@ int hpsi_sequence(wvl_plan* p, hipStream_t st, const void* c, const double* V, d
   WVL_CHK(q.pass(OP_MF, 2, A, B));
   WVL_CHK(q.pass(OP_MF, 1, B, B));
   // step 3b and density: y = pot_scale V psi in place
-  if (p->shared) {
-    WVL_CHK(launch_pot_shared(p->prec, p->d_orbs, p->norb, p->M, B, B, V, pot_scale, p->elems, rho,
-                              0, want_e ? rv : nullptr, e_orb ? pp : nullptr, st));
-  } else {
-    WVL_CHK(launch_pot_orb(p->prec, q.gp, p->pp[p->norb], B, B, V, pot_scale, p->elems,
-                           want_e ? pp : nullptr, st));
+  {
+    Mark mk(p, st, ST_POT);
+    if (p->shared) {
+      WVL_CHK(launch_pot_shared(p->prec, p->d_orbs, p->norb, p->M, B, B, V, pot_scale, p->elems,
+                                rho, 0, want_e ? rv : nullptr, e_orb ? pp : nullptr, st));
+    } else {
+      WVL_CHK(launch_pot_orb(p->prec, q.gp, p->pp[p->norb], B, B, V, pot_scale, p->elems,
+                             want_e ? pp : nullptr, st));
+    }
   }
   // step 3c: x' = Omega^T y (z: B -> A, y: A -> B, x: B -> B)
   WVL_CHK(q.pass(OP_MFT, 3, B, A));
@@ -415,6 +457,7 @@ int hpsi_sequence(wvl_plan* p, hipStream_t st, const void* c, const double* V, d
   WVL_CHK(q.pass(OP_ANA, 2, B, A));
   WVL_CHK(q.pass(OP_ANA, 1, A, hpsi));
   if (want_e) {
+    Mark mk(p, st, ST_ENERGY);
     const int pot_mode = p->shared ? (e_orb ? 2 : 0) : 1;
     WVL_CHK(launch_orb_sums(p->d_orbs, p->norb, p->d_pz, p->d_py, p->d_px, ez, ey, ex, pp, pot_mode,
                             p->d_pp, p->nblk, eorb, st));
@@ -519,8 +562,10 @@ int wvl_local_hpsi(wvl_plan* p, const void* c, const double* V, double pot_scale
     if (p->gexec) { (void)hipGraphExecDestroy(p->gexec); p->gexec = nullptr; }
     hipGraph_t g;
     WVL_HIP(hipStreamBeginCapture(p->gstream, hipStreamCaptureModeThreadLocal));
+    p->capturing = true;
     int r = hpsi_sequence(p, p->gstream, c, V, pot_scale, kin_scale, hpsi, rho, e_loc, e_kin,
                           e_orb, ws);
+    p->capturing = false;
     hipError_t e = hipStreamEndCapture(p->gstream, &g);
     if (r != WVL_OK) { if (e == hipSuccess) (void)hipGraphDestroy(g); return r; }
     if (e != hipSuccess) return hipfail(e, "hipStreamEndCapture");
@@ -543,6 +588,7 @@ int wvl_overlap(wvl_plan* p, const void* c, double* S, void* ws, void* stream) {
   if (!p->dense) return fail(WVL_EUNSUPPORTED, "wvl_overlap needs a dense uniform batch");
   if (int r = check_gpu(p)) return r;
   hipStream_t st = (hipStream_t)stream;
+  Mark mk(p, st, ST_OVERLAP);
   hipError_t e = launch_overlap_p(p->prec, c, p->elems, p->norb, p->M, S,
                                   (double*)wsp(ws, p->o_syrk), st);
   if (e != hipSuccess) return hipfail(e, "overlap");
@@ -559,14 +605,23 @@ int wvl_orthonormalize(wvl_plan* p, void* c, double* S, double* L, void* ws, voi
   double* Lw = (double*)wsp(ws, p->o_L);
   double* Li = (double*)wsp(ws, p->o_Li);
   const size_t nn = sizeof(double) * (size_t)p->norb * p->norb;
-  hipError_t e = launch_overlap_p(p->prec, c, p->elems, p->norb, p->M, Lw,
-                                  (double*)wsp(ws, p->o_syrk), st);
+  hipError_t e;
+  {
+    Mark mk(p, st, ST_OVERLAP);
+    e = launch_overlap_p(p->prec, c, p->elems, p->norb, p->M, Lw, (double*)wsp(ws, p->o_syrk), st);
+  }
   if (e != hipSuccess) return hipfail(e, "overlap");
   if (S) WVL_HIP(hipMemcpyAsync(S, Lw, nn, hipMemcpyDeviceToDevice, st));
-  e = launch_cholesky_inv(Lw, Li, p->norb, p->d_info, st);
+  {
+    Mark mk(p, st, ST_CHOL);
+    e = launch_cholesky_inv(Lw, Li, p->norb, p->d_info, st);
+  }
   if (e != hipSuccess) return hipfail(e, "cholesky");
   if (L) WVL_HIP(hipMemcpyAsync(L, Lw, nn, hipMemcpyDeviceToDevice, st));
-  e = launch_trmm_rows_p(p->prec, Li, c, c, p->elems, p->norb, p->M, st);
+  {
+    Mark mk(p, st, ST_TRMM);
+    e = launch_trmm_rows_p(p->prec, Li, c, c, p->elems, p->norb, p->M, st);
+  }
   if (e != hipSuccess) return hipfail(e, "trmm");
   return WVL_OK;
 }
@@ -597,6 +652,37 @@ int wvl_plan_sync(wvl_plan* p, void* stream) {
     return fail(WVL_EINVAL, "overlap matrix not positive definite (pivot %d)", info[0] - 1);
   }
   return WVL_OK;
+}
+
+int wvl_plan_profile(wvl_plan* p, int32_t capacity) {
+  if (int r = check_plan(p)) return r;
+  if (capacity < 0 || capacity > (1 << 20)) return fail(WVL_EINVAL, "profile capacity out of range");
+  p->prof_cap = capacity;
+  p->prof_used = 0;
+  return WVL_OK;
+}
+
+int wvl_plan_profile_read(wvl_plan* p, int32_t* stage, double* ms, int32_t max, int32_t* count) {
+  if (int r = check_plan(p)) return r;
+  if (!count || max < 0 || (max > 0 && (!stage || !ms)))
+    return fail(WVL_EINVAL, "wvl_plan_profile_read: bad arguments");
+  if (int r = check_gpu(p)) return r;
+  const int n = std::min(max, p->prof_used);
+  for (int i = 0; i < n; ++i) {
+    WVL_HIP(hipEventSynchronize(p->prof[i].b));
+    float t = 0.f;
+    WVL_HIP(hipEventElapsedTime(&t, p->prof[i].a, p->prof[i].b));
+    stage[i] = p->prof[i].stage;
+    ms[i] = t;
+  }
+  *count = n;
+  p->prof_used = 0;
+  return WVL_OK;
+}
+
+const char* wvl_stage_name(int32_t stage) {
+  if (stage < 0 || stage >= ST_NSTAGE) return "unknown";
+  return kStageNames[stage];
 }
 
 }  // extern "C"

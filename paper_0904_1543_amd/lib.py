@@ -68,9 +68,11 @@ _SIGS = {
     "wvl_convert": [P, P, I32, P, I32, I64, P],
     "wvl_plan_sync": [P, P],
     "wvl_plan_tuning": [P, ctypes.POINTER(I32), DP, I32],
+    "wvl_plan_profile": [P, I32],
+    "wvl_plan_profile_read": [P, ctypes.POINTER(I32), DP, I32, ctypes.POINTER(I32)],
 }
 
-EXPORTS = list(_SIGS) + ["wvl_last_error", "wvl_version"]
+EXPORTS = list(_SIGS) + ["wvl_last_error", "wvl_version", "wvl_stage_name"]
 
 for _name, _args in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -80,6 +82,12 @@ _lib.wvl_last_error.restype = ctypes.c_char_p
 _lib.wvl_last_error.argtypes = []
 _lib.wvl_version.restype = ctypes.c_char_p
 _lib.wvl_version.argtypes = []
+_lib.wvl_stage_name.restype = ctypes.c_char_p
+_lib.wvl_stage_name.argtypes = [I32]
+
+
+def wvl_stage_name(stage):
+    return _lib.wvl_stage_name(stage).decode()
 
 
 def wvl_last_error():

@@ -210,3 +210,13 @@ class Plan:
 
     def sync(self):
         lib.wvl_plan_sync(self.h, stream_handle())
+
+    def profile(self, capacity):
+        lib.wvl_plan_profile(self.h, int(capacity))
+
+    def profile_read(self, maxrec=1 << 16):
+        st = (ctypes.c_int32 * maxrec)()
+        ms = (ctypes.c_double * maxrec)()
+        n = ctypes.c_int32()
+        lib.wvl_plan_profile_read(self.h, st, ms, maxrec, ctypes.byref(n))
+        return [(lib.wvl_stage_name(st[i]), ms[i]) for i in range(n.value)]
