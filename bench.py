@@ -33,15 +33,21 @@ ESIZE = {"f64": 8, "f32": 4, "f32c": 8}
 TOL = {"f64": 1e-12, "f32": 2e-6, "f32c": 1e-10}
 
 
-def algorithmic_bytes(stage, plan):
+def algorithmic_bytes(stage, plan, variant):
     """Bytes a launch of `stage` must move for the whole batch (each value
     read or written once): a 1D pass reads its input and writes its output;
-    the kinetic passes also read the accumulated K_{p-1}; the potential stage
-    reads psi, V and writes y and rho; the overlap reads the coefficients once."""
+    passes that accumulate (kinetic K_{p-1}, and with the plane kernel the last
+    two z passes) also read the accumulator; the plane kernel reads u and c
+    and writes t and kxy; the potential stage reads psi, V and writes y and
+    rho; the overlap reads the coefficients once."""
     E, es, M = plan.elems, ESIZE[plan.prec], plan.M[0]
-    if stage.startswith("kin_"):
+    if stage == "xy_plane":
+        return 4 * E * es
+    if stage in ("ck_z", "cwt_z") and variant == 1:
         return 3 * E * es
-    if stage[:3] in ("mf_", "mft", "syn", "ana"):
+    if stage.startswith("kin_") or stage.startswith("ck_"):
+        return 3 * E * es
+    if stage[:3] in ("mf_", "mft", "syn", "ana", "cw_", "cwt"):
         return 2 * E * es
     if stage == "potential":
         return 2 * E * es + 2 * M * 8
@@ -114,8 +120,10 @@ def run_precision(prec, C, V, dims, steps, warmup, sample_orbs):
              for k, v in stages.items()}
     hpsi_ms = sum(v[0] for k, v in stages.items()
                   if k not in ("overlap", "cholesky", "trmm")) / steps
+    v = ctypes.c_int32()
+    lib.wvl_plan_tuning(plan.h, ctypes.byref(v), None, 0)
     res = dict(plan=plan, ms_per_step=ms, wall_s=wall, stages=table, hpsi_ms=hpsi_ms, got=got,
-               energies=energies)
+               energies=energies, variant=v.value)
     del c, Vt, out, rho
     return res
 
@@ -180,7 +188,7 @@ def main():
     ms = r["ms_per_step"]
     # dominant kernel of the headline precision
     dom, dstat = max(r["stages"].items(), key=lambda kv: kv[1]["avg_ms"] * kv[1]["launches"])
-    ab = algorithmic_bytes(dom, r["plan"])
+    ab = algorithmic_bytes(dom, r["plan"], r["variant"])
     roof = None
     if ab is not None:
         gbs = ab / (dstat["avg_ms"] * 1e-3) / 1e9
@@ -210,6 +218,7 @@ def main():
         "cpu_baseline": cpu,
         "precisions": {
             p: {"ms_per_step": v["ms_per_step"],
+                "hpsi_variant": "plane-resident" if v["variant"] == 1 else "pass-by-pass",
                 "orbital_gridpoints_per_s": pts / (v["ms_per_step"] * 1e-3),
                 "hpsi_ms": v["hpsi_ms"],
                 "hpsi_orbital_gridpoints_per_s": pts / (v["hpsi_ms"] * 1e-3),

@@ -147,7 +147,7 @@ int wvl_overlap(wvl_plan *plan, const void *c, double *S, void *ws, void *stream
 /* Cholesky orthonormalisation (Sec. 5 step VIII): S = L L^T, c <- L^{-1} c
  * (rows = orbitals), in place.  S and L (nullable, norb x norb row-major)
  * receive the overlap matrix and the lower Cholesky factor.  A non-positive
- * pivot is reported by wvl_plan_sync() as WVL_EINVAL. */
+ * pivot is reported by wvl_plan_sync() as WVL_EINVAL.  Up to 256 orbitals. */
 int wvl_orthonormalize(wvl_plan *plan, void *c, double *S, double *L, void *ws, void *stream);
 
 /* Format conversion of `count` values between WVL_F64, WVL_F32 and WVL_F32C
@@ -158,7 +158,10 @@ int wvl_convert(wvl_ctx *ctx, const void *src, int32_t src_prec, void *dst, int3
 /* Wait for `stream` and report device-side errors of this plan. */
 int wvl_plan_sync(wvl_plan *plan, void *stream);
 
-/* Choice made at plan creation for the hpsi kernels: variant id and the
+/* Choice made at plan creation for the hpsi kernels: variant id (0: one 1D
+ * pass per axis and operator; 1: z passes around the plane-resident kernel,
+ * chosen whenever every orbital's (x, y) plane fits in LDS; setting the
+ * environment variable WVL_NO_PLANE_KERNEL at plan creation forces 0) and the
  * measured time (ms) of each candidate if WVL_AUTOTUNE was given. */
 int wvl_plan_tuning(const wvl_plan *plan, int32_t *variant, double *times_ms, int32_t ntimes);
 

@@ -169,6 +169,52 @@ def kinetic(h):
     return [v[i] * 2 / s2 for i in range(size)]
 
 
+# ---------------------------------------------------------------------------
+# Polyphase form of the 1D operators: y[k] = sum_o F_{k mod 2}(o) x[k - o].
+# Returned as (lo, [row_p0, row_p1]) with rows indexed by o - lo.
+# ---------------------------------------------------------------------------
+def poly(table_fn, lo, hi):
+    return lo, [[table_fn(p, o) for o in range(lo, hi + 1)] for p in (0, 1)]
+
+
+def base_polyphase(h, g, om, r):
+    zero = mp.mpf(0)
+    def tap(arr, j):
+        return arr[j - LO] if LO <= j < LO + 2 * NVM else zero
+    L = len(r) // 2
+    mf = poly(lambda p, o: tap(om, o), -7, 8)
+    mft = poly(lambda p, o: tap(om, -o), -8, 7)
+    syn = poly(lambda p, o: tap(h, o) if (o - p) % 2 == 0 else tap(g, o + 1), -8, 8)
+    ana = poly(lambda p, o: tap(h, -o) if p == 0 else tap(g, 1 - o), -8, 8)
+    kin = poly(lambda p, o: r[o + L], -L, L)
+    return dict(mf=mf, mft=mft, syn=syn, ana=ana, kin=kin)
+
+
+def compose(B, A):
+    """Polyphase table of the operator B(A(x)):
+    C_p(o) = sum_{o2 + o1 = o} B_p(o2) A_{(p - o2) mod 2}(o1)."""
+    blo, brow = B
+    alo, arow = A
+    bhi, ahi = blo + len(brow[0]) - 1, alo + len(arow[0]) - 1
+    lo, hi = blo + alo, bhi + ahi
+    out = [[mp.mpf(0)] * (hi - lo + 1) for _ in (0, 1)]
+    for p in (0, 1):
+        for o2 in range(blo, bhi + 1):
+            b = brow[p][o2 - blo]
+            if b == 0:
+                continue
+            pa = (p - o2) % 2
+            for o1 in range(alo, ahi + 1):
+                out[p][o2 + o1 - lo] += b * arow[pa][o1 - alo]
+    # trim zero columns at both ends
+    while all(out[p][0] == 0 for p in (0, 1)):
+        out = [row[1:] for row in out]
+        lo += 1
+    while all(out[p][-1] == 0 for p in (0, 1)):
+        out = [row[:-1] for row in out]
+    return lo, out
+
+
 def split32(x):
     hi = np.float32(float(x))
     lo = np.float32(float(x - mp.mpf(float(hi))))
@@ -210,6 +256,24 @@ def emit(path):
     text.append(dbl("WVL_OMEGA", om))
     text.append("// r_l = Phi''(l), l = -14..14 (kinetic filter before -1/(2 h^2))")
     text.append(dbl("WVL_KIN", r))
+    P = base_polyphase(h, g, om, r)
+    combos = {
+        # synthesis then magic filter: coarse coefficients -> point values
+        "WVL_CW": compose(P["mf"], P["syn"]),
+        # transposed magic filter then analysis: point values -> coarse coefficients
+        "WVL_CWT": compose(P["ana"], P["mft"]),
+        # analysis o kinetic o synthesis: the kinetic filter on coarse coefficients
+        "WVL_CK": compose(P["ana"], compose(P["kin"], P["syn"])),
+    }
+    for name, (lo, rows) in combos.items():
+        n = len(rows[0])
+        text.append(f"// combined polyphase filter: y[k] = sum_o F[k mod 2][o - lo] x[k - o], o = {lo}..{lo + n - 1}")
+        text.append(f"#define {name}_LO ({lo})")
+        text.append(f"#define {name}_N {n}")
+        text.append(dbl(name + "0", rows[0]))
+        text.append(dbl(name + "1", rows[1]))
+        text.append(flt(name + "0_32", rows[0]))
+        text.append(flt(name + "1_32", rows[1]))
     text.append(flt("WVL_H32", h))
     text.append(flt("WVL_G32", g))
     text.append(flt("WVL_OMEGA32", om))

@@ -6,6 +6,7 @@
 
 #include <math.h>
 #include <stdarg.h>
+#include <stdlib.h>
 #include <stdio.h>
 #include <string.h>
 
@@ -74,18 +75,23 @@ struct wvl_plan {
   int64_t elems = 0;     // elements per packed plane
   int64_t vlen = 0;      // minimal length of a per-orbital V buffer
   std::vector<OrbDev> orbs;
-  std::vector<int32_t> pz, py, px, pp;
+  std::vector<int32_t> pz, py, px, pp, pq;
   int nblk = 0;          // 256-point blocks of the shared grid
+  // plane-resident path of wvl_local_hpsi
+  bool use_xy = false;
+  int xy_m1 = 0, xy_m2 = 0, xy_G = 1, xy_ngroups = 0, xy_blocks = 0, xy_occ = 4;
   // device copies
   OrbDev* d_orbs = nullptr;
   int32_t* d_pz = nullptr;
   int32_t* d_py = nullptr;
   int32_t* d_px = nullptr;
   int32_t* d_pp = nullptr;
+  int32_t* d_pq = nullptr;
   int* d_info = nullptr;
   // workspace layout (byte offsets)
   size_t ws = 0, o_A = 0, o_B = 0, o_S = 0, o_ez = 0, o_ey = 0, o_ex = 0, o_pp = 0, o_rv = 0,
-         o_rho = 0, o_eorb = 0, o_syrk = 0, o_L = 0, o_Li = 0;
+         o_rho = 0, o_eorb = 0, o_syrk = 0, o_L = 0, o_Li = 0, o_T = 0, o_rhop = 0, o_epl = 0,
+         o_kpl = 0;
   // graph cache
   hipStream_t gstream = nullptr;
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
@@ -101,11 +107,16 @@ struct wvl_plan {
 };
 
 // Stage ids for profiling: 1D passes are op * 3 + (axis - 1); then:
-enum { ST_POT = 15, ST_ENERGY = 16, ST_OVERLAP = 17, ST_CHOL = 18, ST_TRMM = 19, ST_NSTAGE = 20 };
+enum { ST_POT = 15, ST_ENERGY = 16, ST_OVERLAP = 17, ST_CHOL = 18, ST_TRMM = 19, ST_XY = 29,
+       ST_RHO = 30, ST_NSTAGE = 31 };
+static int stage_of(int op, int axis) {
+  return op < 5 ? op * 3 + axis - 1 : 20 + (op - 5) * 3 + axis - 1;
+}
 static const char* kStageNames[ST_NSTAGE] = {
     "mf_x", "mf_y", "mf_z", "mft_x", "mft_y", "mft_z", "syn_x", "syn_y", "syn_z",
     "ana_x", "ana_y", "ana_z", "kin_x", "kin_y", "kin_z", "potential", "energies",
-    "overlap", "cholesky", "trmm"};
+    "overlap", "cholesky", "trmm", "cw_x", "cw_y", "cw_z", "cwt_x", "cwt_y", "cwt_z",
+    "ck_x", "ck_y", "ck_z", "xy_plane", "rho_reduce"};
 
 namespace {
 struct Mark {
@@ -260,6 +271,7 @@ int wvl_plan_create(wvl_ctx* ctx, const wvl_orbital* orbs, int32_t norb, int32_t
   p->py.assign(norb + 1, 0);
   p->px.assign(norb + 1, 0);
   p->pp.assign(norb + 1, 0);
+  p->pq.assign(norb + 1, 0);
   for (int b = 0; b < norb; ++b) {
     const OrbDev& d = p->orbs[b];
     const int64_t m1 = d.m[0], m2 = d.m[1], m3 = d.m[2];
@@ -268,9 +280,34 @@ int wvl_plan_create(wvl_ctx* ctx, const wvl_orbital* orbs, int32_t norb, int32_t
     p->py[b + 1] = p->py[b] + (int32_t)((m1 * m3 + kThreads - 1) / kThreads);
     p->px[b + 1] = p->px[b] + (int32_t)((m2 * m3 + R - 1) / R);
     p->pp[b + 1] = p->pp[b] + (int32_t)((m1 * m2 * m3 + kThreads - 1) / kThreads);
+    p->pq[b + 1] = p->pq[b] + (int32_t)m3;
     if (p->pp[b + 1] < 0 || p->pz[b + 1] < 0) { delete p; return fail(WVL_EINVAL, "too many tiles"); }
   }
   p->nblk = p->shared ? (int)((p->M + kThreads - 1) / kThreads) : 0;
+  // plane-resident path: every orbital's (m1, m2) plane must fit the kernel
+  {
+    bool ok = true;
+    for (int b = 0; b < norb; ++b) {
+      p->xy_m1 = std::max(p->xy_m1, p->orbs[b].m[0]);
+      p->xy_m2 = std::max(p->xy_m2, p->orbs[b].m[1]);
+      ok = ok && xy_supported(prec, p->orbs[b].m[0], p->orbs[b].m[1], p->shared);
+    }
+    ok = ok && xy_supported(prec, p->xy_m1, p->xy_m2, p->shared);
+    if (getenv("WVL_NO_PLANE_KERNEL")) ok = false;
+    if (const char* o = getenv("WVL_PLANE_OCCUPANCY")) p->xy_occ = atoi(o) == 2 ? 2 : 4;
+    p->use_xy = ok;
+    p->variant = ok ? 1 : 0;
+    if (p->shared) {
+      const int m3 = p->orbs[0].m[2];
+      p->xy_G = std::max(1, std::min(8, (int)((int64_t)norb * m3 / 1024)));
+      p->xy_ngroups = (norb + p->xy_G - 1) / p->xy_G;
+      p->xy_blocks = p->xy_ngroups * m3;
+    } else {
+      p->xy_G = 1;
+      p->xy_ngroups = 0;
+      p->xy_blocks = p->pq[norb];
+    }
+  }
   // workspace layout
   size_t off = 0;
   const size_t arr = align256((size_t)p->elems * esize(prec));
@@ -289,12 +326,21 @@ int wvl_plan_create(wvl_ctx* ctx, const wvl_orbital* orbs, int32_t norb, int32_t
     p->o_syrk = off; off += align256(sizeof(double) * (size_t)syrk_partials(norb, p->M));
     p->o_L = off; off += align256(sizeof(double) * (size_t)norb * norb);
     p->o_Li = off; off += align256(sizeof(double) * (size_t)norb * norb);
+    p->o_T = off; off += align256(sizeof(double) * (size_t)norb * norb);
+  }
+  if (p->use_xy) {
+    if (p->shared) {
+      p->o_rhop = off;
+      off += align256(sizeof(double) * (size_t)p->xy_ngroups * p->M);
+    }
+    p->o_epl = off; off += align256(sizeof(double) * (size_t)p->pq[norb]);
+    p->o_kpl = off; off += align256(sizeof(double) * (size_t)p->pq[norb]);
   }
   p->ws = off;
   if (!ctx->dry) {
     hipError_t e = hipSetDevice(ctx->device);
     if (e == hipSuccess) e = hipMalloc((void**)&p->d_orbs, sizeof(OrbDev) * norb);
-    if (e == hipSuccess) e = hipMalloc((void**)&p->d_pz, sizeof(int32_t) * (norb + 1) * 4);
+    if (e == hipSuccess) e = hipMalloc((void**)&p->d_pz, sizeof(int32_t) * (norb + 1) * 5);
     if (e == hipSuccess) e = hipMalloc((void**)&p->d_info, sizeof(int) * 4);
     if (e != hipSuccess) {
       wvl_plan_destroy(p);
@@ -303,11 +349,13 @@ int wvl_plan_create(wvl_ctx* ctx, const wvl_orbital* orbs, int32_t norb, int32_t
     p->d_py = p->d_pz + (norb + 1);
     p->d_px = p->d_py + (norb + 1);
     p->d_pp = p->d_px + (norb + 1);
+    p->d_pq = p->d_pp + (norb + 1);
     std::vector<int32_t> all;
     all.insert(all.end(), p->pz.begin(), p->pz.end());
     all.insert(all.end(), p->py.begin(), p->py.end());
     all.insert(all.end(), p->px.begin(), p->px.end());
     all.insert(all.end(), p->pp.begin(), p->pp.end());
+    all.insert(all.end(), p->pq.begin(), p->pq.end());
     e = hipMemcpy(p->d_orbs, p->orbs.data(), sizeof(OrbDev) * norb, hipMemcpyHostToDevice);
     if (e == hipSuccess)
       e = hipMemcpy(p->d_pz, all.data(), sizeof(int32_t) * all.size(), hipMemcpyHostToDevice);
@@ -391,7 +439,7 @@ struct Seq {
   }
   hipError_t pass(int op, int axis, const void* in, void* out, const void* k0 = nullptr,
                   double kmul = 1.0, double* ep = nullptr) {
-    Mark mk(p, st, op * 3 + axis - 1);
+    Mark mk(p, st, stage_of(op, axis));
     const PassGeom& g = axis == 1 ? gx : axis == 2 ? gy : gz;
     const int n = axis == 1 ? p->px[p->norb] : axis == 2 ? p->py[p->norb] : p->pz[p->norb];
     return launch_pass(p->prec, op, axis, g, n, in, out, k0, p->elems, kmul, ep, st);
@@ -425,14 +473,66 @@ int hpsi_sequence(wvl_plan* p, hipStream_t st, const void* c, const double* V, d
   double* rv = (double*)wsp(ws, p->o_rv);
   double* eorb = e_orb ? e_orb : (double*)wsp(ws, p->o_eorb);
   const bool want_e = e_loc || e_kin || e_orb;
-  // step 2: s = S c  (z: c -> A, y: A -> S, x: S -> S)
-  WVL_CHK(q.pass(OP_SYN, 3, c, A));
-  WVL_CHK(q.pass(OP_SYN, 2, A, S));
-  WVL_CHK(q.pass(OP_SYN, 1, S, S));
-  // step 3a: psi = Omega s (z: S -> A, y: A -> B, x: B -> B)
-  WVL_CHK(q.pass(OP_MF, 3, S, A));
-  WVL_CHK(q.pass(OP_MF, 2, A, B));
-  WVL_CHK(q.pass(OP_MF, 1, B, B));
+  if (p->use_xy) {
+    // z pass: u = W_z c; planes: psi, rho, y, t = W_y^T W_x^T y, kxy;
+    // z passes: kxy += K_z c, then Hc = W_z^T t + kxy
+    double* epl = (double*)wsp(ws, p->o_epl);
+    double* kpl = (double*)wsp(ws, p->o_kpl);
+    double* rhop = p->shared ? (double*)wsp(ws, p->o_rhop) : nullptr;
+    WVL_CHK(q.pass(OP_CW, 3, c, A));
+    {
+      Mark mk(p, st, ST_XY);
+      XyArgs xa;
+      xa.orbs = p->d_orbs;
+      xa.pq = p->d_pq;
+      xa.norb = p->norb;
+      xa.shared = p->shared ? 1 : 0;
+      xa.ngroups = p->xy_ngroups;
+      xa.G = p->xy_G;
+      xa.M = p->M;
+      xa.u = A;
+      xa.c = c;
+      xa.t = B;
+      xa.kxy = S;
+      xa.V = V;
+      xa.pot_scale = pot_scale;
+      xa.kin_mul = kin_scale;
+      xa.plane = p->elems;
+      xa.rho_part = rhop;
+      xa.epot = epl;
+      xa.ekin = kpl;
+      xa.occupancy = p->xy_occ;
+      if (p->shared) {
+        for (int slot = 0; slot < p->xy_G; ++slot) {
+          xa.slot = slot;
+          WVL_CHK(launch_xy(p->prec, xa, p->xy_m1, p->xy_m2, p->xy_blocks, st));
+        }
+      } else {
+        xa.slot = 0;
+        WVL_CHK(launch_xy(p->prec, xa, p->xy_m1, p->xy_m2, p->xy_blocks, st));
+      }
+    }
+    if (p->shared && (rho || want_e)) {
+      Mark mk(p, st, ST_RHO);
+      WVL_CHK(launch_rho_reduce(rhop, p->xy_ngroups, p->M, V, rho, want_e ? rv : nullptr, st));
+    }
+    WVL_CHK(q.pass(OP_CK, 3, c, S, S, kin_scale, want_e ? ez : nullptr));
+    WVL_CHK(q.pass(OP_CWT, 3, B, hpsi, S));
+    if (want_e) {
+      Mark mk(p, st, ST_ENERGY);
+      // kinetic: z-pass tiles + per-plane in-plane sums; potential: per plane
+      WVL_CHK(launch_orb_sums(p->d_orbs, p->norb, p->d_pz, p->d_pq, nullptr, ez, kpl, nullptr, epl,
+                              1, p->d_pq, 0, eorb, st));
+      if (e_loc || e_kin)
+        WVL_CHK(launch_totals(p->d_orbs, p->norb, eorb, rv, p->shared ? p->nblk : 0, e_loc, e_kin, st));
+    }
+    return WVL_OK;
+  }
+  // steps 2 + 3a with the combined filter (synthesis then magic filter per
+  // axis): psi = W3 c (z: c -> A, y: A -> B, x: B -> B)
+  WVL_CHK(q.pass(OP_CW, 3, c, A));
+  WVL_CHK(q.pass(OP_CW, 2, A, B));
+  WVL_CHK(q.pass(OP_CW, 1, B, B));
   // step 3b and density: y = pot_scale V psi in place
   {
     Mark mk(p, st, ST_POT);
@@ -444,18 +544,16 @@ int hpsi_sequence(wvl_plan* p, hipStream_t st, const void* c, const double* V, d
                              want_e ? pp : nullptr, st));
     }
   }
-  // step 3c: x' = Omega^T y (z: B -> A, y: A -> B, x: B -> B)
-  WVL_CHK(q.pass(OP_MFT, 3, B, A));
-  WVL_CHK(q.pass(OP_MFT, 2, A, B));
-  WVL_CHK(q.pass(OP_MFT, 1, B, B));
-  // steps 4+5: k = Kin s + x' (K_0 = x'), accumulated axis by axis into A
-  WVL_CHK(q.pass(OP_KIN, 3, S, A, B, kin_scale, want_e ? ez : nullptr));
-  WVL_CHK(q.pass(OP_KIN, 2, S, A, A, kin_scale, want_e ? ey : nullptr));
-  WVL_CHK(q.pass(OP_KIN, 1, S, A, A, kin_scale, want_e ? ex : nullptr));
-  // step 6: Hc = A k (z: A -> B, y: B -> A, x: A -> hpsi)
-  WVL_CHK(q.pass(OP_ANA, 3, A, B));
-  WVL_CHK(q.pass(OP_ANA, 2, B, A));
-  WVL_CHK(q.pass(OP_ANA, 1, A, hpsi));
+  // steps 3c + 6 combined (transposed magic filter then analysis): W3^T y
+  WVL_CHK(q.pass(OP_CWT, 3, B, A));
+  WVL_CHK(q.pass(OP_CWT, 2, A, B));
+  WVL_CHK(q.pass(OP_CWT, 1, B, B));
+  // steps 4 + 5: the kinetic operator on the coefficients, A Kin S per axis,
+  // accumulated onto W3^T y (the K_0 initialisation of the kinetic recursion)
+  WVL_CHK(q.pass(OP_CK, 3, c, A, B, kin_scale, want_e ? ez : nullptr));
+  WVL_CHK(q.pass(OP_CK, 2, c, A, A, kin_scale, want_e ? ey : nullptr));
+  WVL_CHK(q.pass(OP_CK, 1, c, hpsi, A, kin_scale, want_e ? ex : nullptr));
+  (void)S;
   if (want_e) {
     Mark mk(p, st, ST_ENERGY);
     const int pot_mode = p->shared ? (e_orb ? 2 : 0) : 1;
@@ -599,7 +697,7 @@ int wvl_orthonormalize(wvl_plan* p, void* c, double* S, double* L, void* ws, voi
   if (int r = check_plan(p)) return r;
   if (!c || !ws) return fail(WVL_EINVAL, "wvl_orthonormalize: NULL pointer");
   if (!p->dense) return fail(WVL_EUNSUPPORTED, "wvl_orthonormalize needs a dense uniform batch");
-  if (p->norb > 480) return fail(WVL_EUNSUPPORTED, "wvl_orthonormalize supports up to 480 orbitals");
+  if (p->norb > 256) return fail(WVL_EUNSUPPORTED, "wvl_orthonormalize supports up to 256 orbitals");
   if (int r = check_gpu(p)) return r;
   hipStream_t st = (hipStream_t)stream;
   double* Lw = (double*)wsp(ws, p->o_L);
@@ -614,10 +712,15 @@ int wvl_orthonormalize(wvl_plan* p, void* c, double* S, double* L, void* ws, voi
   if (S) WVL_HIP(hipMemcpyAsync(S, Lw, nn, hipMemcpyDeviceToDevice, st));
   {
     Mark mk(p, st, ST_CHOL);
-    e = launch_cholesky_inv(Lw, Li, p->norb, p->d_info, st);
+    double* T = (double*)wsp(ws, p->o_T);
+    e = launch_cholesky_inv(Lw, Li, T, p->norb, p->d_info, st);
+    if (e == hipSuccess) e = launch_linv_offdiag(Lw, Li, T, p->norb, st);
   }
   if (e != hipSuccess) return hipfail(e, "cholesky");
-  if (L) WVL_HIP(hipMemcpyAsync(L, Lw, nn, hipMemcpyDeviceToDevice, st));
+  if (L) {
+    e = launch_chol_factor(Lw, Li, p->norb, L, st);
+    if (e != hipSuccess) return hipfail(e, "cholesky factor");
+  }
   {
     Mark mk(p, st, ST_TRMM);
     e = launch_trmm_rows_p(p->prec, Li, c, c, p->elems, p->norb, p->M, st);

@@ -20,7 +20,12 @@ enum PrecId { F64 = 0, F32 = 1, F32C = 2 };
 // 1D periodic operators along one axis (Sec. 3.1, Eq. "1dconvtrans", and the
 // kinetic recursion of Sec. 3.4).  Every one is written as a polyphase filter
 //     y[k] = sum_{o = OLO}^{OHI} F_{k mod 2}(o) x[(k - o) mod m]
-enum OpKind { OP_MF = 0, OP_MFT = 1, OP_SYN = 2, OP_ANA = 3, OP_KIN = 4 };
+enum OpKind { OP_MF = 0, OP_MFT = 1, OP_SYN = 2, OP_ANA = 3, OP_KIN = 4,
+              // combined filters (the composition of two or three of the above,
+              // Sec. 2.4 last paragraph: synthesis + magic filter, transposed
+              // magic filter + analysis, analysis o kinetic o synthesis)
+              OP_CW = 5, OP_CWT = 6, OP_CK = 7 };
+constexpr int kNumOps = 8;
 
 template <int OP> struct OpWin;
 template <> struct OpWin<OP_MF>  { static constexpr int OLO = -7,  OHI = 8;  };
@@ -28,6 +33,9 @@ template <> struct OpWin<OP_MFT> { static constexpr int OLO = -8,  OHI = 7;  };
 template <> struct OpWin<OP_SYN> { static constexpr int OLO = -8,  OHI = 8;  };
 template <> struct OpWin<OP_ANA> { static constexpr int OLO = -8,  OHI = 8;  };
 template <> struct OpWin<OP_KIN> { static constexpr int OLO = -14, OHI = 14; };
+template <> struct OpWin<OP_CW>  { static constexpr int OLO = WVL_CW_LO,  OHI = WVL_CW_LO + WVL_CW_N - 1; };
+template <> struct OpWin<OP_CWT> { static constexpr int OLO = WVL_CWT_LO, OHI = WVL_CWT_LO + WVL_CWT_N - 1; };
+template <> struct OpWin<OP_CK>  { static constexpr int OLO = WVL_CK_LO,  OHI = WVL_CK_LO + WVL_CK_N - 1; };
 
 // Base-filter lookups with the out-of-window convention (zero outside j = -7..8).
 __host__ __device__ constexpr int tapidx(int j) { return j - WVL_TAP_LO; }
@@ -41,8 +49,24 @@ __host__ __device__ constexpr bool intap(int j) { return j >= WVL_TAP_LO && j < 
 //  ANA: y[2i] = sum_j h_j s[2i + j], y[2i+1] = sum_j g_j s[2i + j]
 //       -> p = 0: h_{-o} ;  p = 1: g_{1-o}
 //  KIN: F(o) = r_o (the -1/(2h^2) factor is applied to the sum)
+//  CW, CWT, CK: generated tables of the compositions (kinetic: before the
+//  -1/(2h^2) factor)
 template <int OP>
 __host__ __device__ constexpr double coef(int p, int o, int part) {
+  if (OP == OP_CW || OP == OP_CWT || OP == OP_CK) {
+    const int lo = OP == OP_CW ? WVL_CW_LO : OP == OP_CWT ? WVL_CWT_LO : WVL_CK_LO;
+    const int n = OP == OP_CW ? WVL_CW_N : OP == OP_CWT ? WVL_CWT_N : WVL_CK_N;
+    const int i = o - lo;
+    if (i < 0 || i >= n) return 0.0;
+    if (OP == OP_CW)
+      return p == 0 ? (part == 0 ? WVL_CW0[i] : part == 1 ? (double)WVL_CW0_32_HI[i] : (double)WVL_CW0_32_LO[i])
+                    : (part == 0 ? WVL_CW1[i] : part == 1 ? (double)WVL_CW1_32_HI[i] : (double)WVL_CW1_32_LO[i]);
+    if (OP == OP_CWT)
+      return p == 0 ? (part == 0 ? WVL_CWT0[i] : part == 1 ? (double)WVL_CWT0_32_HI[i] : (double)WVL_CWT0_32_LO[i])
+                    : (part == 0 ? WVL_CWT1[i] : part == 1 ? (double)WVL_CWT1_32_HI[i] : (double)WVL_CWT1_32_LO[i]);
+    return p == 0 ? (part == 0 ? WVL_CK0[i] : part == 1 ? (double)WVL_CK0_32_HI[i] : (double)WVL_CK0_32_LO[i])
+                  : (part == 0 ? WVL_CK1[i] : part == 1 ? (double)WVL_CK1_32_HI[i] : (double)WVL_CK1_32_LO[i]);
+  }
   int j = 0;
   int which = 0;  // 0 h, 1 g, 2 omega, 3 kinetic
   bool zero = false;
@@ -88,7 +112,7 @@ struct PassGeom {
 
 constexpr int kThreads = 256;          // threads per workgroup for the pass kernels
 constexpr int kContigLds = 4096;       // LDS values per x-pass tile
-constexpr int kHalo = 16;              // periodic halo kept on each side in LDS
+constexpr int kHalo = 32;              // periodic halo kept on each side in LDS
 
 __device__ __forceinline__ void find_tile(const int32_t* prefix, int norb, int tile, int& b, int& t) {
   int lo = 0, hi = norb;  // prefix[lo] <= tile < prefix[hi]

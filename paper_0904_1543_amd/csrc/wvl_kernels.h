@@ -66,13 +66,52 @@ hipError_t launch_convert(const void* src, int sp, void* dst, int dp, int64_t n,
 // can be captured in graphs).
 hipError_t launch_fill(double* dst, int64_t n, double v, hipStream_t st);
 
+// In-plane part of the local Hamiltonian (one z-plane per workgroup):
+// psi = W_x W_y u, rho/e_pot, t = W_y^T W_x^T (pot_scale V psi),
+// kxy = kin_mul (K_x + K_y) c.  See wvl_xy.hip.
+struct XyArgs {
+  const OrbDev* orbs;
+  const int32_t* pq;     // plane prefix: slot of (b, z) is pq[b] + z
+  int32_t norb;
+  int32_t shared;        // shared potential: orbital groups of G, rho partials
+  int32_t ngroups, G;
+  int64_t M;             // points of the shared grid
+  const void* u;
+  const void* c;
+  void* t;
+  void* kxy;
+  const double* V;
+  double pot_scale, kin_mul;
+  int64_t plane;
+  double* rho_part;      // [ngroups][M] (shared) or nullptr
+  double* epot;          // per (orbital, plane)
+  double* ekin;          // per (orbital, plane): <c, (K_x + K_y) c> over the plane
+  int32_t occupancy;     // waves per SIMD the kernel is compiled for (2 or 4)
+  int32_t slot;          // shared: orbital g * G + slot of every group g
+};
+size_t xy_lds_bytes(int prec, int m1, int m2, bool shared);
+bool xy_supported(int prec, int m1, int m2, bool shared);
+// m1, m2: the plane of every orbital of the launch (the largest one for uneven
+// batches; LDS is sized for it)
+hipError_t launch_xy(int prec, const XyArgs& a, int m1, int m2, int nblocks, hipStream_t st);
+hipError_t launch_rho_reduce(const double* part, int ngroups, int64_t M, const double* V,
+                             double* rho, double* rvpart, hipStream_t st);
+
 // Overlap S = X X^T (X: norb rows of `len` coefficients stored in precision
 // `prec`, plane stride `plane`), Cholesky S = L L^T with L^{-1}, and
 // Y = L^{-1} X.  syrk_partials: workspace of the overlap in doubles.
 int64_t syrk_partials(int norb, int64_t len);
 hipError_t launch_overlap_p(int prec, const void* X, int64_t plane, int norb, int64_t len,
                             double* S, double* work, hipStream_t st);
-hipError_t launch_cholesky_inv(double* S_to_L, double* Linv, int norb, int* info, hipStream_t st);
+// Blocked Cholesky: S (n x n, overwritten with L, upper part not touched
+// except diagonal blocks), Linv diagonal blocks, T scratch (n x n).
+hipError_t launch_cholesky_inv(double* S, double* Linv, double* T, int n, int* info,
+                               hipStream_t st);
+// Off-diagonal blocks of Linv from L and the diagonal inverse blocks.
+hipError_t launch_linv_offdiag(const double* L, double* Linv, double* T, int n, hipStream_t st);
+// L output: the lower triangle of the factorised S.
+hipError_t launch_chol_factor(const double* S, const double* Linv, int norb, double* L,
+                              hipStream_t st);
 hipError_t launch_trmm_rows_p(int prec, const double* Li, const void* X, void* Y, int64_t plane,
                               int norb, int64_t len, hipStream_t st);
 

@@ -5,13 +5,17 @@
 // matrix S = X X^T (X: one row of coefficients per orbital) is factorised as
 // S = L L^T and the orbitals are replaced by the rows of L^{-1} X.  The paper
 // runs the SYRK on the GPU and the factorisation on the host; here everything
-// stays on the GPU:
-//  * SYRK on the float64 matrix cores (v_mfma_f64_16x16x4f64): each workgroup
-//    takes a slice of the coefficient axis, stages 256 orbitals x 8
-//    coefficients at a time in LDS and accumulates one 64x64 block of S per wave; the
-//    slices' partial matrices are summed in a fixed order (deterministic);
-//  * Cholesky and the triangular inverse: one workgroup, right-looking, the
-//    matrix held in global memory (it fits in L2);
+// stays on the GPU, in float64:
+//  * SYRK on the float64 matrix cores (v_mfma_f64_16x16x4f64).  One wave owns
+//    a 64x64 block of the lower triangle of S over a slice of the coefficient
+//    axis.  A matrix-core step sums over 4 coefficients; since the sum over
+//    coefficients does not depend on their order, lane group q of a step takes
+//    coefficient 4q + s of a 16-coefficient chunk for both operands, so every
+//    lane loads 4 consecutive values and each orbital row is read as whole
+//    128-byte lines.  The blocks of one slice are placed on one XCD so the
+//    slice is fetched into one L2.  Slice partials are summed in a fixed order;
+//  * blocked Cholesky and L^{-1} with 64 x 64 diagonal blocks factorised in
+//    LDS and small float64 products for the panels and the trailing updates;
 //  * X <- L^{-1} X on the matrix cores, skipping the zero blocks of L^{-1}.
 
 #include "wvl_kernels.h"
@@ -20,101 +24,121 @@ namespace wvl {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
-constexpr int kSyrkRows = 256;   // orbitals per row block
-constexpr int kSyrkK = 8;        // coefficients staged per step
-constexpr int kSyrkPitch = kSyrkK + 1;
-constexpr int kSyrkSlice = 4096; // coefficients per workgroup
+constexpr int kBlk = 64;        // rows of an S block (one wave)
+constexpr int kSlice = 2048;    // coefficients per wave
+constexpr int kXcd = 8;         // XCDs of the MI355X
+
+__host__ __device__ inline int nblk64(int norb) { return (norb + kBlk - 1) / kBlk; }
+__host__ __device__ inline int ntri(int nb) { return nb * (nb + 1) / 2; }
 
 int64_t syrk_partials(int norb, int64_t len) {
-  const int64_t nslice = (len + kSyrkSlice - 1) / kSyrkSlice;
-  const int64_t nb = (norb + kSyrkRows - 1) / kSyrkRows;
-  return nslice * nb * nb * kSyrkRows * kSyrkRows;
+  const int64_t nslice = (len + kSlice - 1) / kSlice;
+  return nslice * ntri(nblk64(norb)) * kBlk * kBlk;
 }
 
-// One workgroup: rows [I*256, +256) x cols [J*256, +256) of S over coefficient
-// slice `blockIdx.x`; 16 waves, wave w owns the 64x64 sub-block (w/4, w%4).
+// 4 consecutive coefficients of one row as float64 (zero outside the matrix)
 template <int P>
-__global__ __launch_bounds__(1024) void k_syrk(const void* __restrict__ X, int64_t plane, int norb,
-                                               int64_t len, double* __restrict__ part) {
+__device__ __forceinline__ void load4(const void* X, int64_t plane, int64_t row, int norb,
+                                      int64_t len, int64_t k, double v[4]) {
   using T = Prec<P>;
-  __shared__ double A[kSyrkRows * kSyrkPitch];
-  __shared__ double B[kSyrkRows * kSyrkPitch];
-  const int nb = (norb + kSyrkRows - 1) / kSyrkRows;
-  const int I = blockIdx.y / nb, J = blockIdx.y % nb;
-  const int64_t k0 = (int64_t)blockIdx.x * kSyrkSlice;
-  const int64_t k1 = min(len, k0 + (int64_t)kSyrkSlice);
-  const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int wr = wid >> 2, wc = wid & 3;
+  #pragma unroll
+  for (int s = 0; s < 4; ++s) v[s] = 0.0;
+  if (row >= norb) return;
+  const int64_t base = row * len + k;
+  if (k + 3 < len) {
+    #pragma unroll
+    for (int s = 0; s < 4; ++s) v[s] = T::d(T::ldc(X, base + s, plane));
+  } else {
+    #pragma unroll
+    for (int s = 0; s < 4; ++s)
+      if (k + s < len) v[s] = T::d(T::ldc(X, base + s, plane));
+  }
+}
+
+// grid: one wave per (slice, lower-triangle block); the blocks of one slice
+// share blockIdx.x mod 8, i.e. run on one XCD.
+template <int P>
+__global__ __launch_bounds__(64) void k_syrk(const void* __restrict__ X, int64_t plane, int norb,
+                                             int64_t len, int nslice, double* __restrict__ part) {
+  const int nb = nblk64(norb), nt = ntri(nb);
+  const int b = blockIdx.x;
+  const int xcd = b % kXcd, r = b / kXcd;         // r-th block placed on this XCD
+  const int sgrp = r / nt, tri = r % nt;
+  const int slice = sgrp * kXcd + xcd;
+  if (slice >= nslice) return;
+  int I = 0;                                      // tri -> (I, J), I >= J
+  while ((I + 1) * (I + 2) / 2 <= tri) ++I;
+  const int J = tri - I * (I + 1) / 2;
+  const int lane = threadIdx.x;
+  const int li = lane & 15, q = lane >> 4;
+  const int64_t k0 = (int64_t)slice * kSlice;
+  const int64_t k1 = min(len, k0 + (int64_t)kSlice);
   d4 acc[4][4];
   #pragma unroll
   for (int a = 0; a < 4; ++a)
     #pragma unroll
     for (int c = 0; c < 4; ++c) acc[a][c] = d4{0.0, 0.0, 0.0, 0.0};
-  for (int64_t kb = k0; kb < k1; kb += kSyrkK) {
-    // stage 256 rows x 32 coefficients of the I and J row blocks
-    for (int e = threadIdx.x; e < kSyrkRows * kSyrkK; e += 1024) {
-      const int r = e / kSyrkK, c = e % kSyrkK;
-      const int64_t kk = kb + c;
-      const int ra = I * kSyrkRows + r, rb = J * kSyrkRows + r;
-      A[r * kSyrkPitch + c] = (ra < norb && kk < k1) ? T::d(T::ldc(X, (int64_t)ra * len + kk, plane)) : 0.0;
-      B[r * kSyrkPitch + c] = (rb < norb && kk < k1) ? T::d(T::ldc(X, (int64_t)rb * len + kk, plane)) : 0.0;
-    }
-    __syncthreads();
+  for (int64_t k = k0; k < k1; k += 16) {
+    double av[4][4], bv[4][4];
     #pragma unroll
-    for (int ks = 0; ks < kSyrkK; ks += 4) {
-      double av[4], bv[4];
-      // operand layouts: A tile 16x4 -> lane = i + 16 k; B tile 4x16 -> lane = j + 16 k
+    for (int t = 0; t < 4; ++t) {
+      load4<P>(X, plane, (int64_t)I * kBlk + t * 16 + li, norb, len, k + 4 * q, av[t]);
+      if (I != J) load4<P>(X, plane, (int64_t)J * kBlk + t * 16 + li, norb, len, k + 4 * q, bv[t]);
+    }
+    if (I == J) {
       #pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        av[t] = A[(wr * 64 + t * 16 + (lane & 15)) * kSyrkPitch + ks + (lane >> 4)];
-        bv[t] = B[(wc * 64 + t * 16 + (lane & 15)) * kSyrkPitch + ks + (lane >> 4)];
-      }
+      for (int t = 0; t < 4; ++t)
+        #pragma unroll
+        for (int s = 0; s < 4; ++s) bv[t][s] = av[t][s];
+    }
+    #pragma unroll
+    for (int s = 0; s < 4; ++s)
       #pragma unroll
       for (int a = 0; a < 4; ++a)
         #pragma unroll
         for (int c = 0; c < 4; ++c)
-          acc[a][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[c], acc[a][c], 0, 0, 0);
-    }
-    __syncthreads();
+          acc[a][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a][s], bv[c][s], acc[a][c], 0, 0, 0);
   }
-  // result layout of a 16x16 tile (checked on the device): element (i, j) is in
-  // lane j + 16 (i mod 4), register i / 4
-
-  double* dst = part + ((int64_t)blockIdx.x * nb * nb + blockIdx.y) * kSyrkRows * kSyrkRows;
+  // tile element (i, j) is in lane j + 16 (i mod 4), register i / 4 (checked on the device)
+  double* dst = part + ((int64_t)slice * nt + tri) * kBlk * kBlk;
   #pragma unroll
   for (int a = 0; a < 4; ++a)
     #pragma unroll
     for (int c = 0; c < 4; ++c)
       #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int row = wr * 64 + a * 16 + (lane >> 4) + 4 * v;
-        const int col = wc * 64 + c * 16 + (lane & 15);
-        dst[row * kSyrkRows + col] = acc[a][c][v];
+        const int row = a * 16 + q + 4 * v;
+        const int col = c * 16 + li;
+        dst[row * kBlk + col] = acc[a][c][v];
       }
 }
 
-// S[i][j] = sum over slices, fixed order; writes the full symmetric matrix.
+// S[i][j] (and S[j][i]) = sum over slices in slice order.
 __global__ void k_syrk_reduce(const double* __restrict__ part, int norb, int nslice,
                               double* __restrict__ S) {
-  const int nb = (norb + kSyrkRows - 1) / kSyrkRows;
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (int64_t)norb * norb) return;
   const int i = (int)(idx / norb), j = (int)(idx % norb);
-  const int I = i / kSyrkRows, J = j / kSyrkRows;
-  const int64_t blk = (int64_t)I * nb + J;
-  const int r = i % kSyrkRows, c = j % kSyrkRows;
+  if (j > i) return;
+  const int nt = ntri(nblk64(norb));
+  const int I = i / kBlk, J = j / kBlk;
+  const int tri = I * (I + 1) / 2 + J;
+  const int r = i % kBlk, c = j % kBlk;
   double s = 0.0;
-  for (int q = 0; q < nslice; ++q)
-    s += part[((int64_t)q * nb * nb + blk) * kSyrkRows * kSyrkRows + r * kSyrkRows + c];
-  S[idx] = s;
+  for (int q = 0; q < nslice; ++q) s += part[((int64_t)q * nt + tri) * kBlk * kBlk + r * kBlk + c];
+  S[(int64_t)i * norb + j] = s;
+  S[(int64_t)j * norb + i] = s;
 }
 
 template <int P>
 static hipError_t overlap_p(const void* X, int64_t plane, int norb, int64_t len, double* S,
                             double* work, hipStream_t st) {
-  const int nb = (norb + kSyrkRows - 1) / kSyrkRows;
-  const int nslice = (int)((len + kSyrkSlice - 1) / kSyrkSlice);
-  hipLaunchKernelGGL((k_syrk<P>), dim3(nslice, nb * nb), dim3(1024), 0, st, X, plane, norb, len, work);
+  const int nt = ntri(nblk64(norb));
+  const int nslice = (int)((len + kSlice - 1) / kSlice);
+  const int ngrp = (nslice + kXcd - 1) / kXcd;
+  const int64_t nwg = (int64_t)ngrp * nt * kXcd;
+  hipLaunchKernelGGL((k_syrk<P>), dim3((unsigned)nwg), dim3(64), 0, st, X, plane, norb, len, nslice,
+                     work);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int64_t n2 = (int64_t)norb * norb;
@@ -133,119 +157,234 @@ hipError_t launch_overlap_p(int prec, const void* X, int64_t plane, int norb, in
 }
 
 // ---------------------------------------------------------------------------
-// Cholesky S = L L^T (lower, in place) and Linv = L^{-1}; one workgroup.
-// info[0] = 0 on success, j+1 if the j-th pivot is not positive.
+// Blocked Cholesky S = L L^T and Linv = L^{-1} (n <= 256, blocks of 64).
+// For block column J: the diagonal block is factorised and inverted in LDS by
+// one workgroup; the panel below is L_IJ = S_IJ inv(L_JJ)^T; the trailing
+// lower triangle is updated S_IK -= L_IJ L_KJ^T.  Then block row I of Linv is
+// Linv_I,0:I = -inv(L_II) (L_I,0:I Linv_0:I,0:I).  All small products use one
+// strided float64 GEMM kernel; results are deterministic.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(1024) void k_cholesky_inv(double* S, double* Li, int n, int* info) {
-  __shared__ int bad;
-  if (threadIdx.x == 0) bad = 0;
-  __syncthreads();
-  const int tid = threadIdx.x;
-  for (int j = 0; j < n; ++j) {
-    if (tid == 0) {
-      const double d = S[(int64_t)j * n + j];
-      if (!(d > 0.0)) { if (!bad) bad = j + 1; S[(int64_t)j * n + j] = 1.0; }
-      else S[(int64_t)j * n + j] = sqrt(d);
-    }
-    __syncthreads();
-    const double djj = S[(int64_t)j * n + j];
-    for (int i = j + 1 + tid; i < n; i += 1024) S[(int64_t)i * n + j] /= djj;
-    __syncthreads();
-    const int ti = tid >> 5, tk = tid & 31;
-    for (int i = j + 1 + ti; i < n; i += 32) {
-      const double sij = S[(int64_t)i * n + j];
-      for (int k = j + 1 + tk; k <= i; k += 32) S[(int64_t)i * n + k] -= sij * S[(int64_t)k * n + j];
-    }
-    __syncthreads();
-  }
-  // zero the strict upper triangle so that S holds exactly L
-  for (int64_t e = tid; e < (int64_t)n * n; e += 1024) {
-    const int i = (int)(e / n), k = (int)(e % n);
-    if (k > i) S[e] = 0.0;
+constexpr int kCb = 64;
+
+// diagonal block at (r0, r0) of size b <= 64: L_JJ in place (upper part
+// zeroed), inv(L_JJ) to D (leading dimension ldd).  info[0] = first bad pivot + 1.
+__global__ __launch_bounds__(256) void k_potrf_block(double* A, int lda, int r0, int b, double* D,
+                                                     int ldd, int* info) {
+  __shared__ double a[kCb][kCb];
+  __shared__ double m[kCb][kCb];
+  const int t = threadIdx.x;
+  for (int e = t; e < b * b; e += 256) {
+    const int i = e / b, k = e % b;
+    a[i][k] = A[(int64_t)(r0 + i) * lda + r0 + k];
+    m[i][k] = (i == k) ? 1.0 : 0.0;
   }
   __syncthreads();
-  // Linv: row by row, Li[i][c] = (delta_ic - sum_{k=c}^{i-1} L[i][k] Li[k][c]) / L[i][i]
-  for (int i = 0; i < n; ++i) {
-    const double lii = S[(int64_t)i * n + i];
-    for (int c = tid; c < n; c += 1024) {
-      double v = 0.0;
-      if (c <= i) {
-        double s = (c == i) ? 1.0 : 0.0;
-        for (int k = c; k < i; ++k) s -= S[(int64_t)i * n + k] * Li[(int64_t)k * n + c];
-        v = s / lii;
-      }
-      Li[(int64_t)i * n + c] = v;
+  // right-looking unblocked Cholesky in LDS
+  for (int j = 0; j < b; ++j) {
+    double d = a[j][j];
+    if (!(d > 0.0)) {
+      if (t == 0 && info[0] == 0) info[0] = r0 + j + 1;
+      d = 1.0;
+    }
+    const double l = sqrt(d);
+    __syncthreads();
+    if (t == 0) a[j][j] = l;
+    for (int i = j + 1 + t; i < b; i += 256) a[i][j] /= l;
+    __syncthreads();
+    for (int e = t; e < b * b; e += 256) {
+      const int i = e / b, k = e % b;
+      if (k > j && k <= i) a[i][k] -= a[i][j] * a[k][j];
     }
     __syncthreads();
   }
-  if (tid == 0) info[0] = bad;
+  // inverse by forward elimination on [L | I]
+  for (int j = 0; j < b; ++j) {
+    const double inv = 1.0 / a[j][j];
+    __syncthreads();
+    for (int k = t; k <= j; k += 256) m[j][k] *= inv;
+    __syncthreads();
+    for (int e = t; e < b * b; e += 256) {
+      const int i = e / b, k = e % b;
+      if (i > j && k <= j) m[i][k] -= a[i][j] * m[j][k];
+    }
+    __syncthreads();
+  }
+  for (int e = t; e < b * b; e += 256) {
+    const int i = e / b, k = e % b;
+    A[(int64_t)(r0 + i) * lda + r0 + k] = (k <= i) ? a[i][k] : 0.0;
+    D[(int64_t)i * ldd + k] = (k <= i) ? m[i][k] : 0.0;
+  }
 }
 
-hipError_t launch_cholesky_inv(double* S_to_L, double* Linv, int norb, int* info, hipStream_t st) {
-  hipLaunchKernelGGL(k_cholesky_inv, dim3(1), dim3(1024), 0, st, S_to_L, Linv, norb, info);
+// C[i][j] = beta C[i][j] + alpha sum_k A[i*ar + k*ac] B[k*br + j*bc], i < M, j < N
+// (lower != 0: only j <= i + diag).  One thread per element.
+__global__ void k_gemm_s(double* C, int ldc, const double* A, int64_t ar, int64_t ac,
+                         const double* B, int64_t br, int64_t bc, int M, int N, int K,
+                         double alpha, double beta, int lower, int diag) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)M * N) return;
+  const int i = (int)(idx / N), j = (int)(idx % N);
+  if (lower && j > i + diag) return;
+  double s = 0.0;
+  for (int k = 0; k < K; ++k) s = __builtin_fma(A[i * ar + k * ac], B[k * br + j * bc], s);
+  double* c = C + (int64_t)i * ldc + j;
+  *c = (beta == 0.0 ? 0.0 : beta * *c) + alpha * s;
+}
+
+static hipError_t gemm_s(double* C, int ldc, const double* A, int64_t ar, int64_t ac,
+                         const double* B, int64_t br, int64_t bc, int M, int N, int K, double alpha,
+                         double beta, int lower, int diag, hipStream_t st) {
+  if (M <= 0 || N <= 0) return hipSuccess;
+  const int64_t tot = (int64_t)M * N;
+  hipLaunchKernelGGL(k_gemm_s, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, C, ldc, A, ar,
+                     ac, B, br, bc, M, N, K, alpha, beta, lower, diag);
+  return hipGetLastError();
+}
+
+__global__ void k_copy2d(double* __restrict__ dst, int ldd, const double* __restrict__ src, int lds,
+                         int M, int N) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)M * N) return;
+  const int i = (int)(idx / N), j = (int)(idx % N);
+  dst[(int64_t)i * ldd + j] = src[(int64_t)i * lds + j];
+}
+
+__global__ void k_zero_upper_copy(const double* __restrict__ src, double* __restrict__ dst, int n) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)n * n) return;
+  const int i = (int)(idx / n), k = (int)(idx % n);
+  dst[idx] = (k <= i) ? src[idx] : 0.0;
+}
+
+// S (n x n, overwritten with L), Linv (n x n), T: n x n scratch, info[0] = 0 on entry.
+hipError_t launch_cholesky_inv(double* S, double* Linv, double* T, int n, int* info,
+                               hipStream_t st) {
+  if (n > 256) return hipErrorInvalidValue;
+  hipError_t e = launch_fill(Linv, (int64_t)n * n, 0.0, st);
+  if (e != hipSuccess) return e;
+  const int nb = (n + kCb - 1) / kCb;
+  for (int J = 0; J < nb; ++J) {
+    const int r0 = J * kCb, b = min(kCb, n - r0);
+    double* DJ = Linv + (int64_t)r0 * n + r0;
+    hipLaunchKernelGGL(k_potrf_block, dim3(1), dim3(256), 0, st, S, n, r0, b, DJ, n, info);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const int r1 = r0 + b, rem = n - r1;
+    if (rem <= 0) break;
+    // T = S[r1:, r0:r1] inv(L_JJ)^T; then copy back as the panel of L
+    e = gemm_s(T, b, S + (int64_t)r1 * n + r0, n, 1, DJ, 1, n, rem, b, b, 1.0, 0.0, 0, 0, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_copy2d, dim3((unsigned)((rem * b + 255) / 256)), dim3(256), 0, st,
+                       S + (int64_t)r1 * n + r0, n, (const double*)T, b, rem, b);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    // trailing lower triangle: S[r1:, r1:] -= P P^T, P = panel (rem x b)
+    e = gemm_s(S + (int64_t)r1 * n + r1, n, S + (int64_t)r1 * n + r0, n, 1,
+               S + (int64_t)r1 * n + r0, 1, n, rem, rem, b, -1.0, 1.0, 1, 0, st);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_linv_offdiag(const double* L, double* Linv, double* T, int n, hipStream_t st) {
+  hipError_t e;
+  const int nb = (n + kCb - 1) / kCb;
+  for (int I = 1; I < nb; ++I) {
+    const int r0 = I * kCb, b = min(kCb, n - r0);
+    // T (b x r0) = L[r0:r0+b, 0:r0] Linv[0:r0, 0:r0]
+    e = gemm_s(T, r0, L + (int64_t)r0 * n, n, 1, Linv, n, 1, b, r0, r0, 1.0, 0.0, 0, 0, st);
+    if (e != hipSuccess) return e;
+    // Linv[r0:r0+b, 0:r0] = -inv(L_II) T
+    e = gemm_s(Linv + (int64_t)r0 * n, n, Linv + (int64_t)r0 * n + r0, n, 1, T, r0, 1, b, r0, b, -1.0,
+               0.0, 0, 0, st);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_chol_factor(const double* S, const double* Linv, int norb, double* L,
+                              hipStream_t st) {
+  const int64_t n2 = (int64_t)norb * norb;
+  hipLaunchKernelGGL(k_zero_upper_copy, dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, st, S, L,
+                     norb);
+  (void)Linv;
   return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
-// Y = Linv X (rows = orbitals); Linv lower triangular.  Workgroup: all rows x
-// 16 coefficients; 16 waves, wave w owns output row tiles {w, w+16, ...} of 16
-// rows.  Y may alias X (each workgroup reads its
-// columns into LDS before writing).
+// Y = Linv X (rows = orbitals), Linv lower triangular, n <= 256.  Workgroup:
+// 4 waves x 64 columns.  Wave w owns the 16-row tiles {w, 7-w, 8+w, 15-w}
+// (equal work: tile t needs t+1 chunks of 16 k) and all 4 column tiles.
+// Y may alias X: every wave has finished reading before any wave writes.
 // ---------------------------------------------------------------------------
-constexpr int kTrCols = 16;
+constexpr int kTrCols = 64;
 
 template <int P>
-__global__ __launch_bounds__(1024) void k_trmm(const double* __restrict__ Li, const void* X,
-                                               void* Y, int64_t plane, int norb, int64_t len) {
+__global__ __launch_bounds__(256) void k_trmm(const double* __restrict__ Li, const void* X, void* Y,
+                                              int64_t plane, int n, int64_t len) {
   using T = Prec<P>;
-  extern __shared__ double sx[];  // [nrow_pad][kTrCols + 1]
-  const int npad = (norb + 15) & ~15;
-  const int pitch = kTrCols + 1;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int li = lane & 15, q = lane >> 4;
   const int64_t c0 = (int64_t)blockIdx.x * kTrCols;
-  for (int e = threadIdx.x; e < npad * kTrCols; e += 1024) {
-    const int r = e / kTrCols, c = e % kTrCols;
-    const int64_t cc = c0 + c;
-    sx[r * pitch + c] = (r < norb && cc < len) ? T::d(T::ldc(X, (int64_t)r * len + cc, plane)) : 0.0;
+  const int tiles[4] = {w, 7 - w, 8 + w, 15 - w};
+  const int ntile = (n + 15) / 16;
+  d4 acc[4][4];
+  #pragma unroll
+  for (int a = 0; a < 4; ++a)
+    #pragma unroll
+    for (int c = 0; c < 4; ++c) acc[a][c] = d4{0.0, 0.0, 0.0, 0.0};
+  for (int kc = 0; kc < ntile; ++kc) {
+    // B chunk: rows 16 kc + 4 q + s, columns c0 + 16 c + li
+    double bv[4][4];
+    #pragma unroll
+    for (int c = 0; c < 4; ++c)
+      #pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int k = 16 * kc + 4 * q + s;
+        const int64_t col = c0 + 16 * c + li;
+        bv[c][s] = (k < n && col < len) ? T::d(T::ldc(X, (int64_t)k * len + col, plane)) : 0.0;
+      }
+    #pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      const int ti = tiles[a];
+      if (ti < kc || ti >= ntile) continue;
+      const int row = 16 * ti + li;
+      double av[4];
+      #pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int k = 16 * kc + 4 * q + s;
+        av[s] = (row < n && k < n) ? Li[(int64_t)row * n + k] : 0.0;
+      }
+      #pragma unroll
+      for (int s = 0; s < 4; ++s)
+        #pragma unroll
+        for (int c = 0; c < 4; ++c)
+          acc[a][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s], bv[c][s], acc[a][c], 0, 0, 0);
+    }
   }
   __syncthreads();
-  const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int ntile = npad / 16;
-  for (int ti = wid; ti < ntile; ti += 16) {
-    d4 acc = d4{0.0, 0.0, 0.0, 0.0};
-    const int row = ti * 16 + (lane & 15);
-    // only k < (ti+1)*16 contribute (Linv is lower triangular)
-    for (int k = 0; k < (ti + 1) * 16; k += 4) {
-      const int kk = k + (lane >> 4);
-      const double a = (row < norb && kk < norb) ? Li[(int64_t)row * norb + kk] : 0.0;
-      const double bv = sx[kk * pitch + (lane & 15)];
-      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, acc, 0, 0, 0);
-    }
+  #pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    const int ti = tiles[a];
     #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int r = ti * 16 + (lane >> 4) + 4 * v;
-      const int64_t ca = c0 + (lane & 15);
-      if (r < norb && ca < len) T::st(Y, (int64_t)r * len + ca, plane, T::from_d(acc[v]));
-    }
+    for (int c = 0; c < 4; ++c)
+      #pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = 16 * ti + q + 4 * v;
+        const int64_t col = c0 + 16 * c + li;
+        if (r < n && col < len) T::st(Y, (int64_t)r * len + col, plane, T::from_d(acc[a][c][v]));
+      }
   }
-}
-
-template <int P>
-static hipError_t trmm_p(const double* Li, const void* X, void* Y, int64_t plane, int norb,
-                         int64_t len, hipStream_t st) {
-  const int npad = (norb + 15) & ~15;
-  const size_t lds = (size_t)npad * (kTrCols + 1) * sizeof(double);
-  const int64_t nblk = (len + kTrCols - 1) / kTrCols;
-  hipLaunchKernelGGL((k_trmm<P>), dim3((unsigned)nblk), dim3(1024), lds, st, Li, X, Y, plane, norb, len);
-  return hipGetLastError();
 }
 
 hipError_t launch_trmm_rows_p(int prec, const double* Li, const void* X, void* Y, int64_t plane,
                               int norb, int64_t len, hipStream_t st) {
+  if (norb > 256) return hipErrorInvalidValue;
+  const int64_t nblk = (len + kTrCols - 1) / kTrCols;
   switch (prec) {
-    case F64: return trmm_p<F64>(Li, X, Y, plane, norb, len, st);
-    case F32: return trmm_p<F32>(Li, X, Y, plane, norb, len, st);
-    default:  return trmm_p<F32C>(Li, X, Y, plane, norb, len, st);
+    case F64: hipLaunchKernelGGL((k_trmm<F64>), dim3((unsigned)nblk), dim3(256), 0, st, Li, X, Y, plane, norb, len); break;
+    case F32: hipLaunchKernelGGL((k_trmm<F32>), dim3((unsigned)nblk), dim3(256), 0, st, Li, X, Y, plane, norb, len); break;
+    default:  hipLaunchKernelGGL((k_trmm<F32C>), dim3((unsigned)nblk), dim3(256), 0, st, Li, X, Y, plane, norb, len); break;
   }
+  return hipGetLastError();
 }
 
 }  // namespace wvl

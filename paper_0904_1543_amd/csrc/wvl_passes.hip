@@ -69,7 +69,7 @@ __global__ __launch_bounds__(kThreads) void k_strided(PassGeom g, const void* __
       win[W] = T::ldc(in, base + (int64_t)wrapi(k + 1 - OLO, m) * stride, plane);
       V y0, y1;
       pair_conv<P, OP>(win, y0, y1);
-      if (OP == OP_KIN) {
+      if (OP == OP_KIN || OP == OP_CK) {
         // energies use the unweighted operator; kmul weights the output only
         y0 = T::scale(y0, ks);
         y1 = T::scale(y1, ks);
@@ -133,7 +133,7 @@ __global__ __launch_bounds__(kThreads) void k_contig(PassGeom g, const void* in,
     for (int i = 0; i <= W; ++i) win[i] = src[i];
     V y0, y1;
     pair_conv<P, OP>(win, y0, y1);
-    if (OP == OP_KIN) {
+    if (OP == OP_KIN || OP == OP_CK) {
       y0 = T::scale(y0, ks);
       y1 = T::scale(y1, ks);
       if (EN) en += T::d(win[OHI]) * T::d(y0) + T::d(win[OHI + 1]) * T::d(y1);
@@ -184,7 +184,10 @@ static hipError_t launch_op(int op, int axis, const PassGeom& g, int ntiles, con
     case OP_MFT: return launch_axis<OP_MFT, P>(axis, g, ntiles, in, out, k0, plane, kmul, epart, st);
     case OP_SYN: return launch_axis<OP_SYN, P>(axis, g, ntiles, in, out, k0, plane, kmul, epart, st);
     case OP_ANA: return launch_axis<OP_ANA, P>(axis, g, ntiles, in, out, k0, plane, kmul, epart, st);
-    default:     return launch_axis<OP_KIN, P>(axis, g, ntiles, in, out, k0, plane, kmul, epart, st);
+    case OP_KIN: return launch_axis<OP_KIN, P>(axis, g, ntiles, in, out, k0, plane, kmul, epart, st);
+    case OP_CW:  return launch_axis<OP_CW, P>(axis, g, ntiles, in, out, k0, plane, kmul, epart, st);
+    case OP_CWT: return launch_axis<OP_CWT, P>(axis, g, ntiles, in, out, k0, plane, kmul, epart, st);
+    default:     return launch_axis<OP_CK, P>(axis, g, ntiles, in, out, k0, plane, kmul, epart, st);
   }
 }
 

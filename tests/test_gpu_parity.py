@@ -121,6 +121,37 @@ def test_local_hpsi(case, prec):
 
 
 @pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("case", ["small", "tiny"])
+def test_local_hpsi_pass_by_pass_variant(case, prec, monkeypatch):
+    """The variant with one 1D pass per axis (used when a plane does not fit
+    in LDS) gives the same result."""
+    monkeypatch.setenv("WVL_NO_PLANE_KERNEL", "1")
+    cs, plan = setup(case, prec, potential="gauss16")
+    from paper_0904_1543_amd import lib
+    import ctypes
+    v = ctypes.c_int32()
+    lib.wvl_plan_tuning(plan.h, ctypes.byref(v), None, 0)
+    assert v.value == 0
+    C, V, occ = cs["C"], cs["V"], cs["occ"]
+    r = plan.local_hpsi(plan.pack(C), plan.pack_potential(V), per_orbital=True)
+    ref = W.local_hpsi(C, V, occ)
+    assert batch_rel(plan.unpack(r["hpsi"]), list(ref["hpsi"])) < TOL[prec]
+    assert rel(r["rho"].cpu().numpy(), ref["rho"].ravel()) < TOL[prec]
+    e = r["energies"].cpu().numpy()
+    assert abs(e[0] - ref["e_loc"]) <= TOL[prec] * abs(ref["e_loc"])
+    assert abs(e[1] - ref["e_kin"]) <= TOL[prec] * abs(ref["e_kin"])
+
+
+def test_plane_kernel_is_the_default():
+    cs, plan = setup("ragged", "f64")
+    from paper_0904_1543_amd import lib
+    import ctypes
+    v = ctypes.c_int32()
+    lib.wvl_plan_tuning(plan.h, ctypes.byref(v), None, 0)
+    assert v.value == 1
+
+
+@pytest.mark.parametrize("prec", PRECS)
 def test_local_hpsi_scaled(prec):
     """pot_scale / kin_scale weight the two parts: H' = a Hloc + b Kin."""
     cs, plan = setup("small", prec, seed=9)
