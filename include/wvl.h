@@ -159,9 +159,12 @@ int wvl_convert(wvl_ctx *ctx, const void *src, int32_t src_prec, void *dst, int3
 int wvl_plan_sync(wvl_plan *plan, void *stream);
 
 /* Choice made at plan creation for the hpsi kernels: variant id (0: one 1D
- * pass per axis and operator; 1: z passes around the plane-resident kernel,
- * chosen whenever every orbital's (x, y) plane fits in LDS; setting the
- * environment variable WVL_NO_PLANE_KERNEL at plan creation forces 0) and the
+ * pass per axis and operator; 1: z passes around the plane-resident kernel
+ * with vector-FMA in-plane passes, chosen whenever every orbital's (x, y)
+ * plane fits in LDS; 2: the same with the in-plane passes of WVL_F64 on the
+ * float64 matrix cores, chosen for WVL_F64 when the plane fits their 16 x 16
+ * tiling (up to 128 x 128).  At plan creation the environment variable
+ * WVL_NO_PLANE_KERNEL forces 0 and WVL_XY_VECTOR forces 1 over 2) and the
  * measured time (ms) of each candidate if WVL_AUTOTUNE was given. */
 int wvl_plan_tuning(const wvl_plan *plan, int32_t *variant, double *times_ms, int32_t ntimes);
 

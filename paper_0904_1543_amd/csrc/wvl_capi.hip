@@ -80,6 +80,7 @@ struct wvl_plan {
   // plane-resident path of wvl_local_hpsi
   bool use_xy = false;
   int xy_m1 = 0, xy_m2 = 0, xy_G = 1, xy_ngroups = 0, xy_blocks = 0, xy_occ = 4;
+  int xy_engine = 0;   // in-plane passes: 0 vector FMA, 1 float64 matrix cores
   // device copies
   OrbDev* d_orbs = nullptr;
   int32_t* d_pz = nullptr;
@@ -286,17 +287,18 @@ int wvl_plan_create(wvl_ctx* ctx, const wvl_orbital* orbs, int32_t norb, int32_t
   p->nblk = p->shared ? (int)((p->M + kThreads - 1) / kThreads) : 0;
   // plane-resident path: every orbital's (m1, m2) plane must fit the kernel
   {
-    bool ok = true;
     for (int b = 0; b < norb; ++b) {
       p->xy_m1 = std::max(p->xy_m1, p->orbs[b].m[0]);
       p->xy_m2 = std::max(p->xy_m2, p->orbs[b].m[1]);
-      ok = ok && xy_supported(prec, p->orbs[b].m[0], p->orbs[b].m[1], p->shared);
     }
-    ok = ok && xy_supported(prec, p->xy_m1, p->xy_m2, p->shared);
+    // float64 uses the matrix cores when the plane fits their tiling
+    const bool mx = xy_matrix_engine(prec, p->xy_m1, p->xy_m2) && !getenv("WVL_XY_VECTOR");
+    bool ok = xy_supported(prec, p->xy_m1, p->xy_m2, mx);
     if (getenv("WVL_NO_PLANE_KERNEL")) ok = false;
     if (const char* o = getenv("WVL_PLANE_OCCUPANCY")) p->xy_occ = atoi(o) == 2 ? 2 : 4;
     p->use_xy = ok;
-    p->variant = ok ? 1 : 0;
+    p->xy_engine = ok && mx ? 1 : 0;
+    p->variant = ok ? 1 + p->xy_engine : 0;
     if (p->shared) {
       const int m3 = p->orbs[0].m[2];
       p->xy_G = std::max(1, std::min(8, (int)((int64_t)norb * m3 / 1024)));
@@ -502,6 +504,7 @@ int hpsi_sequence(wvl_plan* p, hipStream_t st, const void* c, const double* V, d
       xa.epot = epl;
       xa.ekin = kpl;
       xa.occupancy = p->xy_occ;
+      xa.engine = p->xy_engine;
       if (p->shared) {
         for (int slot = 0; slot < p->xy_G; ++slot) {
           xa.slot = slot;

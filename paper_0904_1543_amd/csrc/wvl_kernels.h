@@ -88,9 +88,12 @@ struct XyArgs {
   double* ekin;          // per (orbital, plane): <c, (K_x + K_y) c> over the plane
   int32_t occupancy;     // waves per SIMD the kernel is compiled for (2 or 4)
   int32_t slot;          // shared: orbital g * G + slot of every group g
+  int32_t engine;        // 0: vector FMA passes, 1: float64 matrix-core passes
 };
-size_t xy_lds_bytes(int prec, int m1, int m2, bool shared);
-bool xy_supported(int prec, int m1, int m2, bool shared);
+// engine: the float64 matrix-core form of the in-plane passes
+bool xy_matrix_engine(int prec, int m1, int m2);
+size_t xy_lds_bytes(int prec, int m1, int m2, bool engine);
+bool xy_supported(int prec, int m1, int m2, bool engine);
 // m1, m2: the plane of every orbital of the launch (the largest one for uneven
 // batches; LDS is sized for it)
 hipError_t launch_xy(int prec, const XyArgs& a, int m1, int m2, int nblocks, hipStream_t st);

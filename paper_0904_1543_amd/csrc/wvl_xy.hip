@@ -23,11 +23,10 @@
 // a shared potential is accumulated per group of orbitals, in orbital order,
 // in a partial array that the group's workgroup owns (no atomics).
 
-#include "wvl_kernels.h"
+#include "wvl_plane.h"
 
 namespace wvl {
 
-constexpr int kXyThreads = 512;
 constexpr int kU = 4;             // outputs per work item
 constexpr int kCh = 16;           // taps per chunk
 constexpr int kMaxItems = 8;      // work items per thread and pass (m <= 128)
@@ -64,7 +63,6 @@ __device__ __forceinline__ void plane_conv(typename Prec<P>::V* buf, int m1, int
   const int mc = AX == 1 ? m1 : m2;          // conv length
   const int mo = AX == 1 ? m2 : m1;          // number of lines
   const int nseg = (mc + kU - 1) / kU;
-  const bool onewrap = mc >= WMAX;           // a window wraps at most once
   const int estride = AX == 1 ? 1 : pitch;   // LDS elements between neighbours
   ItemIter itr(mo);
   nitems = 0;
@@ -81,23 +79,37 @@ __device__ __forceinline__ void plane_conv(typename Prec<P>::V* buf, int m1, int
     for (int ch = 0; ch < NCH; ++ch) {
       const int olo = OLO + ch * kCh;
       const int ohi = (OLO + ch * kCh + kCh - 1) < OHI ? (OLO + ch * kCh + kCh - 1) : OHI;
-      // window: win[w] = x[k0 - ohi + w], w < kU + ohi - olo
+      // window: win[w] = x[k0 - ohi + w], w < kU + ohi - olo.  Away from the
+      // ends of the line the window is contiguous (constant offsets from one
+      // base); near them it wraps, stepped one index at a time.
+      const int len = kU + ohi - olo;
       V win[WMAX];
-      const int s0 = wrapi(k0 - ohi, mc);
-      #pragma unroll
-      for (int w = 0; w < WMAX; ++w) {
-        if (w < kU + ohi - olo) {
-          int idx = s0 + w;
-          if (onewrap) idx = idx >= mc ? idx - mc : idx;
-          else idx = wrapi(idx, mc);
-          win[w] = lp[idx * estride];
+      int s0 = k0 - ohi;
+      if (s0 >= 0 && s0 + len <= mc) {
+        const V* p = lp + s0 * estride;
+        #pragma unroll
+        for (int w = 0; w < WMAX; ++w)
+          if (w < len) win[w] = p[w * estride];
+      } else {
+        while (s0 < 0) s0 += mc;
+        while (s0 >= mc) s0 -= mc;
+        int off = s0 * estride;
+        const int end = mc * estride;
+        #pragma unroll
+        for (int w = 0; w < WMAX; ++w) {
+          if (w < len) {
+            win[w] = lp[off];
+            off += estride;
+            off = off == end ? 0 : off;
+          }
         }
       }
+      // taps outer, outputs inner: kU independent accumulation chains
       #pragma unroll
-      for (int u = 0; u < kU; ++u) {
+      for (int oo = 0; oo < kCh; ++oo) {
+        const int o = OLO + ch * kCh + oo;
         #pragma unroll
-        for (int oo = 0; oo < kCh; ++oo) {
-          const int o = OLO + ch * kCh + oo;
+        for (int u = 0; u < kU; ++u) {
           if (o <= OHI && coef<OP>(u & 1, o, 0) != 0.0)
             T::template add<OP>(acc[u], u & 1, o, win[u + ohi - o]);
         }
@@ -174,153 +186,277 @@ __device__ __forceinline__ double plane_dot(const typename Prec<P>::V* buf, int 
   return e;
 }
 
-// Points of the plane owned by this thread: e = threadIdx.x + k * kXyThreads,
-// with its LDS position y * pitch + x stepped incrementally.
-struct PtIter {
-  int e, x, y, dx, dy, m1;
-  __device__ PtIter(int m1_) : m1(m1_) {
-    e = threadIdx.x;
-    x = threadIdx.x % m1_;
-    y = threadIdx.x / m1_;
-    dx = kXyThreads % m1_;
-    dy = kXyThreads / m1_;
+// ---------------------------------------------------------------------------
+// Engines: how one 1D pass over the plane in LDS is computed.  conv<OP, AX>
+// leaves the pass's outputs in registers (Res); store writes them back in
+// place (after a barrier: every input must have been read first), dot sums
+// x * result over the output positions (x: the pass's input there), and
+// store_global_y writes the results of an AX = 2 pass to a plane in memory.
+
+// Vector FMA engine (every precision): work items of U outputs of one line.
+template <int P, int MI>
+struct VecEngine {
+  using T = Prec<P>;
+  using V = typename T::V;
+  struct Res { V r[MI][kU]; int n; };
+  __device__ __forceinline__ static int pitch(int m1) { return m1 + 1; }
+  template <int OP, int AX>
+  __device__ __forceinline__ static void conv(V* buf, int m1, int m2, int pitch, Res& r) {
+    plane_conv<OP, P, AX, MI>(buf, m1, m2, pitch, r.r, r.n);
   }
-  __device__ int pos(int pitch) const { return y * pitch + x; }
-  __device__ void next() {
-    e += kXyThreads;
-    x += dx;
-    y += dy;
-    if (x >= m1) { x -= m1; ++y; }
+  template <int AX>
+  __device__ __forceinline__ static void store(V* buf, int m1, int m2, int pitch, const Res& r) {
+    plane_store<P, AX, MI>(buf, m1, m2, pitch, r.r, r.n, false);
+  }
+  template <int AX>
+  __device__ __forceinline__ static double dot(const V* buf, int m1, int m2, int pitch, const Res& r) {
+    return plane_dot<P, AX, MI>(buf, m1, m2, pitch, r.r, r.n);
+  }
+  __device__ __forceinline__ static void scale(Res& r, double s) {
+    #pragma unroll
+    for (int it = 0; it < MI; ++it)
+      #pragma unroll
+      for (int u = 0; u < kU; ++u) r.r[it][u] = T::scale(r.r[it][u], s);
+  }
+  __device__ __forceinline__ static void store_global_y(void* dst, int64_t gp, int64_t plane, int m1, int m2,
+                                        const Res& r) {
+    ItemIter itr(m1);
+    #pragma unroll
+    for (int it = 0; it < MI; ++it) {
+      if (it >= r.n) break;
+      #pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        const int y = itr.seg * kU + u;
+        if (y < m2) T::st(dst, gp + (int64_t)y * m1 + itr.line, plane, r.r[it][u]);
+      }
+      itr.next();
+    }
   }
 };
 
-__device__ __forceinline__ double xy_block_sum(double v) {
-  __shared__ double red[kXyThreads / 64];
-  #pragma unroll
-  for (int s = 32; s > 0; s >>= 1) v += __shfl_xor(v, s, 64);
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  if (lane == 0) red[wid] = v;
-  __syncthreads();
-  double t = 0.0;
-  #pragma unroll
-  for (int w = 0; w < kXyThreads / 64; ++w) t += red[w];
-  __syncthreads();
-  return t;
+// Matrix-core engine (float64): a pass is a product with a banded circulant
+// matrix, F[k][j] = F_{k mod 2}(k - j) (mod m), applied to the plane from the
+// left (y) or the right (x).  It is cut into 16 x 16 output tiles; a tile
+// needs 16 + OHI - OLO inputs along the pass, i.e. S steps of the
+// 16 x 16 x 4 float64 matrix instruction, whose filter operand is the same
+// for every tile (k0 is a multiple of 16, so the output parity is that of the
+// row in the tile).  For step s, lane l = n + 16 kk holds F at tap
+// o = n - kk + OHI - 4 s (zero outside the window): as the B operand of an
+// x-pass (B[kk][n]) and as the A operand of a y-pass (A[n][kk]).
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+template <int OP>
+struct Frag {
+  static constexpr int OLO = OpWin<OP>::OLO, OHI = OpWin<OP>::OHI;
+  static constexpr int S = (16 + OHI - OLO + 3) / 4;
+  double v[S][64];
+  constexpr Frag() : v() {
+    for (int s = 0; s < S; ++s)
+      for (int l = 0; l < 64; ++l) {
+        const int n = l & 15, kk = l >> 4;
+        v[s][l] = coef<OP>(n & 1, n - kk + OHI - 4 * s, 0);
+      }
+  }
+};
+__device__ const Frag<OP_CW> kFragCW = Frag<OP_CW>();
+__device__ const Frag<OP_CWT> kFragCWT = Frag<OP_CWT>();
+__device__ const Frag<OP_CK> kFragCK = Frag<OP_CK>();
+template <int OP> __device__ __forceinline__ const double* frag_tab() {
+  return OP == OP_CW ? &kFragCW.v[0][0] : OP == OP_CWT ? &kFragCWT.v[0][0] : &kFragCK.v[0][0];
 }
 
-// Grid: shared-potential batches (SHARED): blockIdx.x = z * ngroups + g
-// (orbitals g*G .. g*G+G-1), the group's density accumulated in LDS after the
-// plane; otherwise one (orbital, plane) per block via the plane prefix pq.
-// Slot of (b, z) in the per-plane energy arrays: pq[b] + z.  MI: work items
-// per thread and pass (planes up to 96 x 96: 3, up to 128 x 128: 4).
+constexpr int kXyWaves = kXyThreads / 64;
+
+template <int MT>
+struct MfEngine {
+  using T = Prec<F64>;
+  using V = double;
+  struct Res { d4 r[MT]; int n; };
+  // rows of 4 (mod 32) doubles: the x-pass operand (16 rows x 4 columns) and
+  // the tile stores fall on distinct banks
+  __device__ __forceinline__ static int pitch(int m1) { return m1 + ((36 - (m1 & 31)) & 31); }
+  // tile t of this wave: output block k0 along the pass, line block o0
+  __device__ __forceinline__ static void tile_of(int t, int nbo, int& k0, int& o0) {
+    const int tile = (threadIdx.x >> 6) + t * kXyWaves;
+    const int bc = tile / nbo;
+    k0 = bc * 16;
+    o0 = (tile - bc * nbo) * 16;
+  }
+  template <int OP, int AX>
+  __device__ __forceinline__ static void conv(V* buf, int m1, int m2, int pitch, Res& r) {
+    constexpr int S = Frag<OP>::S, OHI = Frag<OP>::OHI;
+    const int lane = threadIdx.x & 63, li = lane & 15, q = lane >> 4;
+    const int mc = AX == 1 ? m1 : m2, mo = AX == 1 ? m2 : m1;
+    const int nbo = (mo + 15) >> 4, nt = ((mc + 15) >> 4) * nbo;
+    const int es = AX == 1 ? 1 : pitch;
+    double fc[S];
+    const double* ft = frag_tab<OP>();
+    #pragma unroll
+    for (int s = 0; s < S; ++s) fc[s] = ft[s * 64 + lane];
+    r.n = 0;
+    #pragma unroll
+    for (int t = 0; t < MT; ++t) {
+      if ((threadIdx.x >> 6) + t * kXyWaves >= nt) break;
+      r.n = t + 1;
+      int k0, o0;
+      tile_of(t, nbo, k0, o0);
+      const int line = min(o0 + li, mo - 1);      // rows/columns past the end: unused outputs
+      const V* lp = AX == 1 ? buf + line * pitch : buf + line;
+      // input index of step s: (k0 - OHI + 4 s + q) mod mc; lines are at
+      // least 4 long, so a step wraps at most once (branch-free)
+      int j = (k0 - OHI + q) % mc;
+      j = j < 0 ? j + mc : j;
+      double x[S];
+      #pragma unroll
+      for (int s = 0; s < S; ++s) {
+        x[s] = lp[__mul24(j, es)];
+        j += 4;
+        j = j >= mc ? j - mc : j;
+      }
+      d4 acc = {0.0, 0.0, 0.0, 0.0};
+      #pragma unroll
+      for (int s = 0; s < S; ++s)
+        acc = AX == 1 ? __builtin_amdgcn_mfma_f64_16x16x4f64(x[s], fc[s], acc, 0, 0, 0)
+                      : __builtin_amdgcn_mfma_f64_16x16x4f64(fc[s], x[s], acc, 0, 0, 0);
+      r.r[t] = acc;
+    }
+  }
+  // output element (i, n) of a tile is in lane n + 16 (i mod 4), register i / 4
+  template <int AX, typename F>
+  __device__ __forceinline__ static void each(int m1, int m2, const Res& r, F&& f) {
+    const int lane = threadIdx.x & 63, li = lane & 15, q = lane >> 4;
+    const int mc = AX == 1 ? m1 : m2, mo = AX == 1 ? m2 : m1;
+    const int nbo = (mo + 15) >> 4;
+    #pragma unroll
+    for (int t = 0; t < MT; ++t) {
+      if (t >= r.n) break;
+      int k0, o0;
+      tile_of(t, nbo, k0, o0);
+      #pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        // x-pass: row o0 + i, column k0 + n;  y-pass: row k0 + i, column o0 + n
+        const int i = q + 4 * v;
+        const int k = AX == 1 ? k0 + li : k0 + i;
+        const int o = AX == 1 ? o0 + i : o0 + li;
+        if (k < mc && o < mo) f(AX == 1 ? o : k, AX == 1 ? k : o, r.r[t][v]);
+      }
+    }
+  }
+  template <int AX>
+  __device__ __forceinline__ static void store(V* buf, int m1, int m2, int pitch, const Res& r) {
+    each<AX>(m1, m2, r, [&](int y, int x, double val) { buf[y * pitch + x] = val; });
+  }
+  template <int AX>
+  __device__ __forceinline__ static double dot(const V* buf, int m1, int m2, int pitch, const Res& r) {
+    double e = 0.0;
+    each<AX>(m1, m2, r, [&](int y, int x, double val) { e += buf[y * pitch + x] * val; });
+    return e;
+  }
+  __device__ __forceinline__ static void scale(Res& r, double s) {
+    #pragma unroll
+    for (int t = 0; t < MT; ++t) r.r[t] *= s;
+  }
+  __device__ __forceinline__ static void store_global_y(void* dst, int64_t gp, int64_t plane, int m1, int m2,
+                                        const Res& r) {
+    each<2>(m1, m2, r, [&](int y, int x, double val) {
+      T::st(dst, gp + (int64_t)y * m1 + x, plane, val);
+    });
+  }
+};
+
+template <typename E, int OP, int AX>
+__device__ __forceinline__ void eng_pass(typename E::V* buf, int m1, int m2, int pitch) {
+  typename E::Res r;
+  E::template conv<OP, AX>(buf, m1, m2, pitch, r);
+  __syncthreads();
+  E::template store<AX>(buf, m1, m2, pitch, r);
+  __syncthreads();
+}
+
 // One (orbital, plane): everything the kernel does for orbital b at plane z.
-template <int P, int MI, bool SHARED>
-__device__ __forceinline__ void xy_orbital_plane(const XyArgs& a, int b, int z, int g,
-                                                           int bi) {
+template <int P, typename E, bool SHARED>
+__device__ __forceinline__ void xy_orbital_plane(const XyArgs& a, int b, int z, int g, int bi) {
   using T = Prec<P>;
   using V = typename T::V;
   extern __shared__ __align__(16) unsigned char xy_lds[];
   V* buf = reinterpret_cast<V*>(xy_lds);
-    // every orbital of a group has the same plane; taking the sizes from the
-    // orbital's own descriptor keeps the index arithmetic inside the loop
-    const OrbDev od = a.orbs[b];
-    const int m1 = od.m[0], m2 = od.m[1];
-    const int pitch = m1 + 1;
-    const int npl = m1 * m2;
-    const double ks1 = od.kscale[0], ks2 = od.kscale[1];
-    const int64_t gp = od.off + (int64_t)z * npl;     // plane start in the batch buffers
-    // ---- psi = W_x W_y u
-    for (PtIter q(m1); q.e < npl; q.next()) buf[q.pos(pitch)] = T::ldc(a.u, gp + q.e, a.plane);
+  const OrbDev od = a.orbs[b];
+  const int m1 = od.m[0], m2 = od.m[1];
+  const int pitch = E::pitch(m1);
+  const int npl = m1 * m2;
+  const double ks1 = od.kscale[0], ks2 = od.kscale[1];
+  const int64_t gp = od.off + (int64_t)z * npl;     // plane start in the batch buffers
+  // ---- psi = W_x W_y u
+  plane_batched<kPlaneBatch>(m1, npl, pitch, [&](int e) { return T::ldc(a.u, gp + e, a.plane); },
+                            [&](int, int pos, V v) { buf[pos] = v; });
+  __syncthreads();
+  eng_pass<E, OP_CW, 2>(buf, m1, m2, pitch);
+  eng_pass<E, OP_CW, 1>(buf, m1, m2, pitch);
+  // ---- pointwise stage: rho (group partial, fixed orbital order), e_pot,
+  //      y = pot_scale V psi
+  double ep = 0.0;
+  const double* Vp = a.V + od.voff + (int64_t)z * npl;
+  double* rp = SHARED ? a.rho_part + (int64_t)g * a.M + (int64_t)z * npl : nullptr;
+  struct VR { double v, r; };
+  plane_batched<kPlaneBatch>(
+      m1, npl, pitch,
+      [&](int e) { return VR{Vp[e], SHARED && rp && bi != 0 ? rp[e] : 0.0}; },
+      [&](int e, int pos, VR w) {
+        const V psi = buf[pos];
+        const double pd = T::d(psi);
+        if (SHARED && rp) rp[e] = bi == 0 ? od.occ * pd * pd : __builtin_fma(od.occ * pd, pd, w.r);
+        ep = __builtin_fma(w.v * pd, pd, ep);
+        buf[pos] = T::scale(psi, w.v * a.pot_scale);
+      });
+  __syncthreads();
+  // ---- t = W_y^T W_x^T y
+  eng_pass<E, OP_CWT, 1>(buf, m1, m2, pitch);
+  eng_pass<E, OP_CWT, 2>(buf, m1, m2, pitch);
+  for (PtIter q(m1); q.e < npl; q.next()) T::st(a.t, gp + q.e, a.plane, buf[q.pos(pitch)]);
+  __syncthreads();
+  // ---- kxy = (K_x + K_y) c, and <c, (K_x + K_y) c> for the kinetic energy:
+  //      K_y c goes straight to kxy, K_x c through LDS once c is no longer
+  //      needed, then kxy += the LDS plane
+  plane_batched<kPlaneBatch>(m1, npl, pitch, [&](int e) { return T::ldc(a.c, gp + e, a.plane); },
+                            [&](int, int pos, V v) { buf[pos] = v; });
+  __syncthreads();
+  double ek = 0.0;
+  {
+    typename E::Res r;
+    E::template conv<OP_CK, 2>(buf, m1, m2, pitch, r);
+    E::scale(r, ks2);
+    ek += E::template dot<2>(buf, m1, m2, pitch, r);
+    if (a.kin_mul != 1.0) E::scale(r, a.kin_mul);
+    E::store_global_y(a.kxy, gp, a.plane, m1, m2, r);
+  }
+  {
+    typename E::Res r;
+    E::template conv<OP_CK, 1>(buf, m1, m2, pitch, r);
+    E::scale(r, ks1);
+    ek += E::template dot<1>(buf, m1, m2, pitch, r);
+    if (a.kin_mul != 1.0) E::scale(r, a.kin_mul);
     __syncthreads();
-    plane_pass<OP_CW, P, 2, MI>(buf, m1, m2, pitch);
-    plane_pass<OP_CW, P, 1, MI>(buf, m1, m2, pitch);
-    // ---- pointwise stage: rho (group partial, fixed orbital order), e_pot,
-    //      y = pot_scale V psi
-    double ep = 0.0;
-    const double* Vp = a.V + od.voff + (int64_t)z * npl;
-    double* rp = SHARED ? a.rho_part + (int64_t)g * a.M + (int64_t)z * npl : nullptr;
-    for (PtIter q(m1); q.e < npl; q.next()) {
-      const int pos = q.pos(pitch), e = q.e;
-      const V psi = buf[pos];
-      const double pd = T::d(psi);
-      const double v = Vp[e];
-      if (SHARED && rp) rp[e] = bi == 0 ? od.occ * pd * pd : __builtin_fma(od.occ * pd, pd, rp[e]);
-      ep = __builtin_fma(v * pd, pd, ep);
-      buf[pos] = T::scale(psi, v * a.pot_scale);
-    }
-    __syncthreads();
-    // ---- t = W_y^T W_x^T y
-    plane_pass<OP_CWT, P, 1, MI>(buf, m1, m2, pitch);
-    plane_pass<OP_CWT, P, 2, MI>(buf, m1, m2, pitch);
-    for (PtIter q(m1); q.e < npl; q.next()) T::st(a.t, gp + q.e, a.plane, buf[q.pos(pitch)]);
-    __syncthreads();
-    // ---- kxy = (K_x + K_y) c, and <c, (K_x + K_y) c> for the kinetic energy:
-    //      K_y c goes straight to kxy (lanes along x: coalesced), K_x c through
-    //      LDS once c is no longer needed, then kxy += the LDS plane
-    for (PtIter q(m1); q.e < npl; q.next()) buf[q.pos(pitch)] = T::ldc(a.c, gp + q.e, a.plane);
-    __syncthreads();
-    double ek = 0.0;
-    {
-      V r[MI][kU];
-      int n = 0;
-      plane_conv<OP_CK, P, 2, MI>(buf, m1, m2, pitch, r, n);
-      #pragma unroll
-      for (int it = 0; it < MI; ++it)
-        #pragma unroll
-        for (int u = 0; u < kU; ++u) r[it][u] = T::scale(r[it][u], ks2);
-      ek += plane_dot<P, 2, MI>(buf, m1, m2, pitch, r, n);
-      ItemIter itr(m1);
-      #pragma unroll
-      for (int it = 0; it < MI; ++it) {
-        if (it >= n) break;
-        #pragma unroll
-        for (int u = 0; u < kU; ++u) {
-          const int y = itr.seg * kU + u;
-          if (y < m2) {
-            const V val = a.kin_mul != 1.0 ? T::scale(r[it][u], a.kin_mul) : r[it][u];
-            T::st(a.kxy, gp + (int64_t)y * m1 + itr.line, a.plane, val);
-          }
-        }
-        itr.next();
-      }
-    }
-    {
-      V r[MI][kU];
-      int n = 0;
-      plane_conv<OP_CK, P, 1, MI>(buf, m1, m2, pitch, r, n);
-      #pragma unroll
-      for (int it = 0; it < MI; ++it)
-        #pragma unroll
-        for (int u = 0; u < kU; ++u) r[it][u] = T::scale(r[it][u], ks1);
-      ek += plane_dot<P, 1, MI>(buf, m1, m2, pitch, r, n);
-      if (a.kin_mul != 1.0) {
-        #pragma unroll
-        for (int it = 0; it < MI; ++it)
-          #pragma unroll
-          for (int u = 0; u < kU; ++u) r[it][u] = T::scale(r[it][u], a.kin_mul);
-      }
-      __syncthreads();
-      plane_store<P, 1, MI>(buf, m1, m2, pitch, r, n, false);
-    }
-    __syncthreads();
-    for (PtIter q(m1); q.e < npl; q.next()) {
-      const V kx = buf[q.pos(pitch)];
-      T::st(a.kxy, gp + q.e, a.plane, T::plus(T::ldc(a.kxy, gp + q.e, a.plane), kx));
-    }
-    // ---- per-(orbital, plane) energies (the block sums end with a barrier)
-    const double sp = xy_block_sum(ep);
-    const double sk = xy_block_sum(ek);
-    if (threadIdx.x == 0) {
-      a.epot[a.pq[b] + z] = sp;
-      a.ekin[a.pq[b] + z] = sk;
-    }
+    E::template store<1>(buf, m1, m2, pitch, r);
+  }
+  __syncthreads();
+  plane_batched<kPlaneBatch>(m1, npl, pitch, [&](int e) { return T::ldc(a.kxy, gp + e, a.plane); },
+                            [&](int e, int pos, V ky) {
+                              T::st(a.kxy, gp + e, a.plane, T::plus(ky, buf[pos]));
+                            });
+  // ---- per-(orbital, plane) energies (the block sums end with a barrier)
+  const double sp = xy_block_sum(ep);
+  const double sk = xy_block_sum(ek);
+  if (threadIdx.x == 0) {
+    a.epot[a.pq[b] + z] = sp;
+    a.ekin[a.pq[b] + z] = sk;
+  }
 }
 
 // Grid: shared-potential batches (SHARED): blockIdx.x = z * ngroups + g and
 // the orbital is g * G + slot (one launch per slot, in slot order, so the
 // group's density partial is accumulated in orbital order); otherwise one
 // (orbital, plane) per block via the plane prefix pq.
-template <int P, int MI, bool SHARED, int WPE>
+template <int P, typename E, bool SHARED, int WPE>
 __global__ __launch_bounds__(kXyThreads) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
 void k_xy(XyArgs a) {
   int b, z, g = 0;
@@ -332,7 +468,7 @@ void k_xy(XyArgs a) {
   } else {
     find_tile(a.pq, a.norb, blockIdx.x, b, z);
   }
-  xy_orbital_plane<P, MI, SHARED>(a, b, z, g, a.slot);
+  xy_orbital_plane<P, E, SHARED>(a, b, z, g, a.slot);
 }
 
 // rho[r] = sum_g rho_part[g][r] (group order), and per-block sums of V rho
@@ -352,41 +488,65 @@ static int xy_items(int m1, int m2) {
   const int it = ix > iy ? ix : iy;
   return (it + kXyThreads - 1) / kXyThreads;
 }
+static int xy_tiles(int m1, int m2) {
+  const int nt = ((m1 + 15) / 16) * ((m2 + 15) / 16);
+  return (nt + kXyWaves - 1) / kXyWaves;
+}
+static int mf_pitch(int m1) { return m1 + ((36 - (m1 & 31)) & 31); }
 
-size_t xy_lds_bytes(int prec, int m1, int m2, bool shared) {
-  (void)shared;
+bool xy_matrix_engine(int prec, int m1, int m2) {
+  return prec == F64 && xy_tiles(m1, m2) <= 8 && (size_t)m2 * mf_pitch(m1) * 8 <= 160 * 1024;
+}
+
+size_t xy_lds_bytes(int prec, int m1, int m2, bool engine) {
+  if (engine) return (size_t)m2 * mf_pitch(m1) * 8;
   return (size_t)m2 * (m1 + 1) * (prec == F32 ? 4 : 8);
 }
 
-bool xy_supported(int prec, int m1, int m2, bool shared) {
-  return xy_items(m1, m2) <= kMaxItems && xy_lds_bytes(prec, m1, m2, shared) <= 160 * 1024;
+bool xy_supported(int prec, int m1, int m2, bool engine) {
+  if (engine) return xy_matrix_engine(prec, m1, m2);
+  return xy_items(m1, m2) <= kMaxItems && xy_lds_bytes(prec, m1, m2, false) <= 160 * 1024;
 }
 
-template <int P, bool SH, int WPE>
-static void xy_launch_w(const XyArgs& a, int mi, int nblocks, size_t lds, hipStream_t st) {
+template <int P, typename E, bool SH>
+static void xy_launch_e(const XyArgs& a, int nblocks, size_t lds, hipStream_t st) {
+  // occupancy target: 4 waves per SIMD (two workgroups per CU, <= 128
+  // registers) or 2 (one workgroup per CU, <= 256 registers)
   const dim3 g(nblocks), b(kXyThreads);
-  if (mi <= 3) hipLaunchKernelGGL((k_xy<P, 3, SH, WPE>), g, b, lds, st, a);
-  else if (mi <= 5) hipLaunchKernelGGL((k_xy<P, 5, SH, WPE>), g, b, lds, st, a);
-  else hipLaunchKernelGGL((k_xy<P, 8, SH, WPE>), g, b, lds, st, a);
+  if (a.occupancy == 2) hipLaunchKernelGGL((k_xy<P, E, SH, 2>), g, b, lds, st, a);
+  else hipLaunchKernelGGL((k_xy<P, E, SH, 4>), g, b, lds, st, a);
 }
 
 template <int P, bool SH>
-static void xy_launch_p(const XyArgs& a, int mi, int nblocks, size_t lds, hipStream_t st) {
-  // occupancy target: 4 waves per SIMD (two workgroups per CU, <= 128
-  // registers) or 2 (one workgroup per CU, <= 256 registers)
-  if (a.occupancy == 2) xy_launch_w<P, SH, 2>(a, mi, nblocks, lds, st);
-  else xy_launch_w<P, SH, 4>(a, mi, nblocks, lds, st);
+static void xy_launch_v(const XyArgs& a, int mi, int nblocks, size_t lds, hipStream_t st) {
+  if (mi <= 3) xy_launch_e<P, VecEngine<P, 3>, SH>(a, nblocks, lds, st);
+  else if (mi <= 5) xy_launch_e<P, VecEngine<P, 5>, SH>(a, nblocks, lds, st);
+  else xy_launch_e<P, VecEngine<P, 8>, SH>(a, nblocks, lds, st);
+}
+
+template <bool SH>
+static void xy_launch_m(const XyArgs& a, int mt, int nblocks, size_t lds, hipStream_t st) {
+  if (mt <= 2) xy_launch_e<F64, MfEngine<2>, SH>(a, nblocks, lds, st);
+  else if (mt <= 5) xy_launch_e<F64, MfEngine<5>, SH>(a, nblocks, lds, st);
+  else xy_launch_e<F64, MfEngine<8>, SH>(a, nblocks, lds, st);
 }
 
 hipError_t launch_xy(int prec, const XyArgs& a, int m1, int m2, int nblocks, hipStream_t st) {
   if (nblocks == 0) return hipSuccess;
-  const int mi = xy_items(m1, m2);
   const bool sh = a.shared != 0;
-  const size_t lds = xy_lds_bytes(prec, m1, m2, sh);
+  const bool mx = a.engine != 0;
+  if (mx && !xy_matrix_engine(prec, m1, m2)) return hipErrorInvalidValue;
+  const size_t lds = xy_lds_bytes(prec, m1, m2, mx);
+  if (mx) {
+    const int mt = xy_tiles(m1, m2);
+    sh ? xy_launch_m<true>(a, mt, nblocks, lds, st) : xy_launch_m<false>(a, mt, nblocks, lds, st);
+    return hipGetLastError();
+  }
+  const int mi = xy_items(m1, m2);
   switch (prec) {
-    case F64: sh ? xy_launch_p<F64, true>(a, mi, nblocks, lds, st) : xy_launch_p<F64, false>(a, mi, nblocks, lds, st); break;
-    case F32: sh ? xy_launch_p<F32, true>(a, mi, nblocks, lds, st) : xy_launch_p<F32, false>(a, mi, nblocks, lds, st); break;
-    default:  sh ? xy_launch_p<F32C, true>(a, mi, nblocks, lds, st) : xy_launch_p<F32C, false>(a, mi, nblocks, lds, st); break;
+    case F64: sh ? xy_launch_v<F64, true>(a, mi, nblocks, lds, st) : xy_launch_v<F64, false>(a, mi, nblocks, lds, st); break;
+    case F32: sh ? xy_launch_v<F32, true>(a, mi, nblocks, lds, st) : xy_launch_v<F32, false>(a, mi, nblocks, lds, st); break;
+    default:  sh ? xy_launch_v<F32C, true>(a, mi, nblocks, lds, st) : xy_launch_v<F32C, false>(a, mi, nblocks, lds, st); break;
   }
   return hipGetLastError();
 }

@@ -127,11 +127,7 @@ def test_local_hpsi_pass_by_pass_variant(case, prec, monkeypatch):
     in LDS) gives the same result."""
     monkeypatch.setenv("WVL_NO_PLANE_KERNEL", "1")
     cs, plan = setup(case, prec, potential="gauss16")
-    from paper_0904_1543_amd import lib
-    import ctypes
-    v = ctypes.c_int32()
-    lib.wvl_plan_tuning(plan.h, ctypes.byref(v), None, 0)
-    assert v.value == 0
+    assert _variant(plan) == 0
     C, V, occ = cs["C"], cs["V"], cs["occ"]
     r = plan.local_hpsi(plan.pack(C), plan.pack_potential(V), per_orbital=True)
     ref = W.local_hpsi(C, V, occ)
@@ -142,13 +138,53 @@ def test_local_hpsi_pass_by_pass_variant(case, prec, monkeypatch):
     assert abs(e[1] - ref["e_kin"]) <= TOL[prec] * abs(ref["e_kin"])
 
 
-def test_plane_kernel_is_the_default():
-    cs, plan = setup("ragged", "f64")
+def _variant(plan):
     from paper_0904_1543_amd import lib
     import ctypes
     v = ctypes.c_int32()
     lib.wvl_plan_tuning(plan.h, ctypes.byref(v), None, 0)
-    assert v.value == 1
+    return v.value
+
+
+@pytest.mark.parametrize("prec,expect", [("f64", 2), ("f32", 1), ("f32c", 1)])
+def test_plane_kernel_is_the_default(prec, expect):
+    """float64 runs its in-plane passes on the matrix cores, the other
+    precisions on the vector units."""
+    cs, plan = setup("ragged", prec)
+    assert _variant(plan) == expect
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_local_hpsi_f64_vector_engine(case, monkeypatch):
+    """The vector-FMA form of the float64 in-plane passes gives the same
+    result as the oracle (and as the matrix-core form)."""
+    monkeypatch.setenv("WVL_XY_VECTOR", "1")
+    cs, plan = setup(case, "f64", potential="gauss16")
+    assert _variant(plan) == 1
+    C, V, occ = cs["C"], cs["V"], cs["occ"]
+    r = plan.local_hpsi(plan.pack(C), plan.pack_potential(V), per_orbital=True)
+    ref = W.local_hpsi(C, V, occ)
+    assert batch_rel(plan.unpack(r["hpsi"]), list(ref["hpsi"])) < TOL["f64"]
+    assert rel(r["rho"].cpu().numpy(), ref["rho"].ravel()) < TOL["f64"]
+    eo = r["e_orb"].cpu().numpy()
+    assert rel(eo[: plan.norb], ref["e_loc_orb"]) < TOL["f64"]
+    assert rel(eo[plan.norb:], ref["e_kin_orb"]) < TOL["f64"]
+
+
+@pytest.mark.parametrize("dims", [(16, 16, 3), (33, 31, 2), (48, 41, 2), (64, 64, 2)])
+def test_local_hpsi_f64_plane_sizes(dims):
+    """Planes that are whole multiples of the 16 x 16 matrix tiles, ragged
+    ones, and the largest supported plane (128 x 128 fine)."""
+    cs = inputs.random_case(21, 2, dims, potential="gauss16")
+    plan = ops.Plan(cs["dims"], prec="f64")
+    assert _variant(plan) == 2
+    C, V, occ = cs["C"], cs["V"], cs["occ"]
+    r = plan.local_hpsi(plan.pack(C), plan.pack_potential(V), per_orbital=True)
+    ref = W.local_hpsi(C, V, occ)
+    assert batch_rel(plan.unpack(r["hpsi"]), list(ref["hpsi"])) < TOL["f64"]
+    e = r["energies"].cpu().numpy()
+    assert abs(e[0] - ref["e_loc"]) <= TOL["f64"] * abs(ref["e_loc"])
+    assert abs(e[1] - ref["e_kin"]) <= TOL["f64"] * abs(ref["e_kin"])
 
 
 @pytest.mark.parametrize("prec", PRECS)
