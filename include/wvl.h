@@ -60,8 +60,18 @@ typedef enum { WVL_F64 = 0, WVL_F32 = 1, WVL_F32C = 2 } wvl_prec;
 /* plan flags */
 #define WVL_SHARED_V   1u  /* all orbitals share one potential (and one grid)   */
 #define WVL_USE_GRAPH  2u  /* record wvl_local_hpsi in a hipGraph and replay it  */
-#define WVL_PERSISTENT 4u  /* run wvl_local_hpsi as one persistent kernel       */
-#define WVL_AUTOTUNE   8u  /* time the tile candidates at plan creation         */
+/* WVL_PERSISTENT: in wvl_local_hpsi's plane-resident sequence the z passes
+ * and (without WVL_SHARED_V) the in-plane kernel run as persistent launches:
+ * as many workgroups as the GPU holds take tiles from a work queue, largest
+ * orbitals first (longest-processing-time-first order), which balances
+ * batches of uneven orbitals.  The queue counters live in the workspace, so
+ * calls that share a workspace must not overlap.
+ * WVL_AUTOTUNE: at plan creation, time the launch-sequence candidates of
+ * wvl_local_hpsi on the plan's own batch (temporary device buffers of about
+ * three batch arrays plus the workspace) and keep the fastest; see
+ * wvl_plan_tuning. */
+#define WVL_PERSISTENT 4u  /* persistent, work-queue launches (see above)        */
+#define WVL_AUTOTUNE   8u  /* time the launch candidates at plan creation       */
 
 typedef struct {
   int32_t n[3];     /* coarse dims n1, n2, n3 (>= 2 each); fine dims are 2n     */
@@ -163,9 +173,14 @@ int wvl_plan_sync(wvl_plan *plan, void *stream);
  * with vector-FMA in-plane passes, chosen whenever every orbital's (x, y)
  * plane fits in LDS; 2: the same with the in-plane passes of WVL_F64 on the
  * float64 matrix cores, chosen for WVL_F64 when the plane fits their 16 x 16
- * tiling (up to 128 x 128).  At plan creation the environment variable
- * WVL_NO_PLANE_KERNEL forces 0 and WVL_XY_VECTOR forces 1 over 2) and the
- * measured time (ms) of each candidate if WVL_AUTOTUNE was given. */
+ * tiling (up to 128 x 128).  Without WVL_AUTOTUNE the environment variable
+ * WVL_NO_PLANE_KERNEL forces 0 and WVL_XY_VECTOR forces 1 over 2; the
+ * variable WVL_PLANE_OCCUPANCY=2 compiles the plane kernel's choice for 2
+ * instead of 4 waves per SIMD.)  With WVL_AUTOTUNE, times_ms[k] (k < ntimes)
+ * receives the mean time of candidate k, or -1 where it was not available:
+ * 0 one pass per axis; 1 plane kernel at 4 waves per SIMD (default engine);
+ * 2 the same at 2 waves per SIMD; 3 plane kernel with the vector engine
+ * (WVL_F64 only).  Without it times_ms is filled with -1. */
 int wvl_plan_tuning(const wvl_plan *plan, int32_t *variant, double *times_ms, int32_t ntimes);
 
 /* Launch profiling: with capacity > 0, every kernel launch of the following

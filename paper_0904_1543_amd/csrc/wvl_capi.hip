@@ -79,8 +79,14 @@ struct wvl_plan {
   int nblk = 0;          // 256-point blocks of the shared grid
   // plane-resident path of wvl_local_hpsi
   bool use_xy = false;
+  bool xy_ok = false;    // some form of the plane path fits (workspace reserved)
   int xy_m1 = 0, xy_m2 = 0, xy_G = 1, xy_ngroups = 0, xy_blocks = 0, xy_occ = 4;
   int xy_engine = 0;   // in-plane passes: 0 vector FMA, 1 float64 matrix cores
+  // persistent launches (WVL_PERSISTENT) of the plane path: work order by
+  // decreasing cost per tile, and the number of resident workgroups
+  bool persistent = false;
+  std::vector<int32_t> perm_z, order_z, perm_q, order_q;
+  int pgrid_pass = 0;
   // device copies
   OrbDev* d_orbs = nullptr;
   int32_t* d_pz = nullptr;
@@ -88,11 +94,12 @@ struct wvl_plan {
   int32_t* d_px = nullptr;
   int32_t* d_pp = nullptr;
   int32_t* d_pq = nullptr;
+  int32_t *d_perm_z = nullptr, *d_order_z = nullptr, *d_perm_q = nullptr, *d_order_q = nullptr;
   int* d_info = nullptr;
   // workspace layout (byte offsets)
   size_t ws = 0, o_A = 0, o_B = 0, o_S = 0, o_ez = 0, o_ey = 0, o_ex = 0, o_pp = 0, o_rv = 0,
          o_rho = 0, o_eorb = 0, o_syrk = 0, o_L = 0, o_Li = 0, o_T = 0, o_rhop = 0, o_epl = 0,
-         o_kpl = 0;
+         o_kpl = 0, o_queue = 0;
   // graph cache
   hipStream_t gstream = nullptr;
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
@@ -156,6 +163,10 @@ static int check_gpu(const wvl_plan* p) {
 }
 
 static inline char* wsp(void* ws, size_t off) { return (char*)ws + off; }
+
+namespace {
+int autotune(wvl_plan* p);
+}  // namespace
 
 extern "C" {
 
@@ -297,6 +308,8 @@ int wvl_plan_create(wvl_ctx* ctx, const wvl_orbital* orbs, int32_t norb, int32_t
     if (getenv("WVL_NO_PLANE_KERNEL")) ok = false;
     if (const char* o = getenv("WVL_PLANE_OCCUPANCY")) p->xy_occ = atoi(o) == 2 ? 2 : 4;
     p->use_xy = ok;
+    p->xy_ok = xy_supported(prec, p->xy_m1, p->xy_m2, mx) ||
+               xy_supported(prec, p->xy_m1, p->xy_m2, false);
     p->xy_engine = ok && mx ? 1 : 0;
     p->variant = ok ? 1 + p->xy_engine : 0;
     if (p->shared) {
@@ -309,6 +322,24 @@ int wvl_plan_create(wvl_ctx* ctx, const wvl_orbital* orbs, int32_t norb, int32_t
       p->xy_ngroups = 0;
       p->xy_blocks = p->pq[norb];
     }
+  }
+  // persistent work order: z-pass tiles cost ~ m3 (one line per lane),
+  // in-plane tiles (one plane) cost ~ m1 m2; largest first, ties by index
+  {
+    auto build = [&](std::vector<int32_t>& perm, std::vector<int32_t>& order,
+                     const std::vector<int32_t>& pre, auto cost) {
+      perm.resize(norb);
+      for (int b = 0; b < norb; ++b) perm[b] = b;
+      std::stable_sort(perm.begin(), perm.end(),
+                       [&](int32_t x, int32_t y) { return cost(x) > cost(y); });
+      order.assign(norb + 1, 0);
+      for (int r = 0; r < norb; ++r) order[r + 1] = order[r] + (pre[perm[r] + 1] - pre[perm[r]]);
+    };
+    build(p->perm_z, p->order_z, p->pz, [&](int b) { return (int64_t)p->orbs[b].m[2]; });
+    build(p->perm_q, p->order_q, p->pq,
+          [&](int b) { return (int64_t)p->orbs[b].m[0] * p->orbs[b].m[1]; });
+    p->persistent = (flags & WVL_PERSISTENT) != 0;
+    p->pgrid_pass = std::max(1, ctx->cus) * 8;
   }
   // workspace layout
   size_t off = 0;
@@ -330,7 +361,7 @@ int wvl_plan_create(wvl_ctx* ctx, const wvl_orbital* orbs, int32_t norb, int32_t
     p->o_Li = off; off += align256(sizeof(double) * (size_t)norb * norb);
     p->o_T = off; off += align256(sizeof(double) * (size_t)norb * norb);
   }
-  if (p->use_xy) {
+  if (p->xy_ok) {   // the plane path may be chosen later by the tuner
     if (p->shared) {
       p->o_rhop = off;
       off += align256(sizeof(double) * (size_t)p->xy_ngroups * p->M);
@@ -338,11 +369,12 @@ int wvl_plan_create(wvl_ctx* ctx, const wvl_orbital* orbs, int32_t norb, int32_t
     p->o_epl = off; off += align256(sizeof(double) * (size_t)p->pq[norb]);
     p->o_kpl = off; off += align256(sizeof(double) * (size_t)p->pq[norb]);
   }
+  p->o_queue = off; off += 256;   // work-queue counters of persistent launches
   p->ws = off;
   if (!ctx->dry) {
     hipError_t e = hipSetDevice(ctx->device);
     if (e == hipSuccess) e = hipMalloc((void**)&p->d_orbs, sizeof(OrbDev) * norb);
-    if (e == hipSuccess) e = hipMalloc((void**)&p->d_pz, sizeof(int32_t) * (norb + 1) * 5);
+    if (e == hipSuccess) e = hipMalloc((void**)&p->d_pz, sizeof(int32_t) * (norb + 1) * 9);
     if (e == hipSuccess) e = hipMalloc((void**)&p->d_info, sizeof(int) * 4);
     if (e != hipSuccess) {
       wvl_plan_destroy(p);
@@ -352,12 +384,20 @@ int wvl_plan_create(wvl_ctx* ctx, const wvl_orbital* orbs, int32_t norb, int32_t
     p->d_px = p->d_py + (norb + 1);
     p->d_pp = p->d_px + (norb + 1);
     p->d_pq = p->d_pp + (norb + 1);
+    p->d_perm_z = p->d_pq + (norb + 1);
+    p->d_order_z = p->d_perm_z + (norb + 1);
+    p->d_perm_q = p->d_order_z + (norb + 1);
+    p->d_order_q = p->d_perm_q + (norb + 1);
     std::vector<int32_t> all;
     all.insert(all.end(), p->pz.begin(), p->pz.end());
     all.insert(all.end(), p->py.begin(), p->py.end());
     all.insert(all.end(), p->px.begin(), p->px.end());
     all.insert(all.end(), p->pp.begin(), p->pp.end());
     all.insert(all.end(), p->pq.begin(), p->pq.end());
+    for (auto* v : {&p->perm_z, &p->order_z, &p->perm_q, &p->order_q}) {
+      all.insert(all.end(), v->begin(), v->end());
+      all.resize(all.size() + (norb + 1 - v->size()), 0);
+    }
     e = hipMemcpy(p->d_orbs, p->orbs.data(), sizeof(OrbDev) * norb, hipMemcpyHostToDevice);
     if (e == hipSuccess)
       e = hipMemcpy(p->d_pz, all.data(), sizeof(int32_t) * all.size(), hipMemcpyHostToDevice);
@@ -367,6 +407,9 @@ int wvl_plan_create(wvl_ctx* ctx, const wvl_orbital* orbs, int32_t norb, int32_t
       wvl_plan_destroy(p);
       return hipfail(e, "plan upload");
     }
+  }
+  if ((flags & WVL_AUTOTUNE) && !ctx->dry) {
+    if (int r = autotune(p)) { wvl_plan_destroy(p); return r; }
   }
   *plan = p;
   return WVL_OK;
@@ -433,6 +476,7 @@ struct Seq {
   wvl_plan* p;
   hipStream_t st;
   PassGeom gz, gy, gx, gp;
+  int32_t* queue = nullptr;   // persistent z passes: next free counter
   Seq(wvl_plan* pl, hipStream_t s) : p(pl), st(s) {
     gz = PassGeom{p->d_orbs, p->d_pz, p->norb};
     gy = PassGeom{p->d_orbs, p->d_py, p->norb};
@@ -442,8 +486,15 @@ struct Seq {
   hipError_t pass(int op, int axis, const void* in, void* out, const void* k0 = nullptr,
                   double kmul = 1.0, double* ep = nullptr) {
     Mark mk(p, st, stage_of(op, axis));
-    const PassGeom& g = axis == 1 ? gx : axis == 2 ? gy : gz;
+    PassGeom g = axis == 1 ? gx : axis == 2 ? gy : gz;
     const int n = axis == 1 ? p->px[p->norb] : axis == 2 ? p->py[p->norb] : p->pz[p->norb];
+    if (axis == 3 && queue) {
+      g.order = p->d_order_z;
+      g.perm = p->d_perm_z;
+      g.queue = queue++;
+      g.ntiles = n;
+      g.grid = p->pgrid_pass;
+    }
     return launch_pass(p->prec, op, axis, g, n, in, out, k0, p->elems, kmul, ep, st);
   }
   // 3D separable operator: z pass in -> out, y pass out -> tmp, x pass tmp -> out
@@ -481,6 +532,12 @@ int hpsi_sequence(wvl_plan* p, hipStream_t st, const void* c, const double* V, d
     double* epl = (double*)wsp(ws, p->o_epl);
     double* kpl = (double*)wsp(ws, p->o_kpl);
     double* rhop = p->shared ? (double*)wsp(ws, p->o_rhop) : nullptr;
+    int32_t* queue = (int32_t*)wsp(ws, p->o_queue);
+    if (p->persistent) {
+      // counters: z passes 0..2, in-plane kernel 3
+      WVL_CHK(launch_fill_int(queue, 4, st));
+      q.queue = queue;
+    }
     WVL_CHK(q.pass(OP_CW, 3, c, A));
     {
       Mark mk(p, st, ST_XY);
@@ -505,6 +562,19 @@ int hpsi_sequence(wvl_plan* p, hipStream_t st, const void* c, const double* V, d
       xa.ekin = kpl;
       xa.occupancy = p->xy_occ;
       xa.engine = p->xy_engine;
+      xa.order = nullptr;
+      xa.perm = nullptr;
+      xa.queue = nullptr;
+      xa.ntiles = p->xy_blocks;
+      int nblocks = p->xy_blocks;
+      if (p->persistent && !p->shared) {
+        xa.order = p->d_order_q;
+        xa.perm = p->d_perm_q;
+        xa.queue = queue + 3;
+        const size_t lds = xy_lds_bytes(p->prec, p->xy_m1, p->xy_m2, p->xy_engine != 0);
+        const int per_cu = std::max(1, std::min(p->xy_occ / 2, (int)(p->ctx->lds_per_block / lds)));
+        nblocks = std::min(nblocks, std::max(1, p->ctx->cus) * per_cu);
+      }
       if (p->shared) {
         for (int slot = 0; slot < p->xy_G; ++slot) {
           xa.slot = slot;
@@ -512,7 +582,7 @@ int hpsi_sequence(wvl_plan* p, hipStream_t st, const void* c, const double* V, d
         }
       } else {
         xa.slot = 0;
-        WVL_CHK(launch_xy(p->prec, xa, p->xy_m1, p->xy_m2, p->xy_blocks, st));
+        WVL_CHK(launch_xy(p->prec, xa, p->xy_m1, p->xy_m2, nblocks, st));
       }
     }
     if (p->shared && (rho || want_e)) {
@@ -566,6 +636,85 @@ int hpsi_sequence(wvl_plan* p, hipStream_t st, const void* c, const double* V, d
       WVL_CHK(launch_totals(p->d_orbs, p->norb, eorb, rv, p->shared ? p->nblk : 0, e_loc, e_kin, st));
   }
   return WVL_OK;
+}
+
+// Candidates of the hpsi launch sequence, timed on the plan's own batch (zero
+// data: no kernel's work depends on values), in this order:
+//   0: one 1D pass per axis and operator;
+//   1: plane-resident kernel, 4 waves per SIMD, default engine;
+//   2: plane-resident kernel, 2 waves per SIMD, default engine;
+//   3: plane-resident kernel, 4 waves per SIMD, vector FMA engine (float64
+//      only, where the matrix-core engine is the default).
+// Unavailable candidates get -1.  The fastest one is kept.
+int autotune(wvl_plan* p) {
+  struct Cand { bool xy; int occ, engine; };
+  const bool mx = xy_matrix_engine(p->prec, p->xy_m1, p->xy_m2);
+  const bool plane_ok = xy_supported(p->prec, p->xy_m1, p->xy_m2, mx);
+  const bool vec_ok = xy_supported(p->prec, p->xy_m1, p->xy_m2, false);
+  const Cand cands[4] = {{false, 4, 0}, {true, 4, mx ? 1 : 0}, {true, 2, mx ? 1 : 0}, {true, 4, 0}};
+  const bool avail[4] = {true, plane_ok, plane_ok, mx && vec_ok};
+  const size_t es = p->prec == WVL_F32 ? 4 : 8;
+  const size_t arr = (size_t)p->elems * es;
+  const size_t vbytes = sizeof(double) * (size_t)(p->shared ? p->M : std::max<int64_t>(p->vlen, 1));
+  void *c = nullptr, *out = nullptr, *ws = nullptr, *V = nullptr, *e = nullptr;
+  hipStream_t st = nullptr;
+  hipEvent_t t0 = nullptr, t1 = nullptr;
+  hipError_t err = hipMalloc(&c, arr);
+  if (err == hipSuccess) err = hipMalloc(&out, arr);
+  if (err == hipSuccess) err = hipMalloc(&ws, p->ws);
+  if (err == hipSuccess) err = hipMalloc(&V, vbytes);
+  if (err == hipSuccess) err = hipMalloc(&e, 4 * sizeof(double));
+  if (err == hipSuccess) err = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+  if (err == hipSuccess) err = hipEventCreate(&t0);
+  if (err == hipSuccess) err = hipEventCreate(&t1);
+  if (err == hipSuccess) err = hipMemsetAsync(c, 0, arr, st);
+  if (err == hipSuccess) err = hipMemsetAsync(V, 0, vbytes, st);
+  int status = WVL_OK;
+  if (err != hipSuccess) status = hipfail(err, "autotune buffers");
+  const Cand keep{p->use_xy, p->xy_occ, p->xy_engine};
+  int best = -1;
+  double best_ms = 0.0;
+  p->tune_ms.assign(4, -1.0);
+  for (int k = 0; k < 4 && status == WVL_OK; ++k) {
+    if (!avail[k]) continue;
+    p->use_xy = cands[k].xy;
+    p->xy_occ = cands[k].occ;
+    p->xy_engine = cands[k].engine;
+    double* ed = (double*)e;
+    status = hpsi_sequence(p, st, c, (const double*)V, 1.0, 1.0, out, nullptr, ed, ed + 1,
+                           nullptr, ws);   // warm-up
+    if (status != WVL_OK) break;
+    constexpr int kReps = 3;
+    err = hipEventRecord(t0, st);
+    for (int r = 0; r < kReps && status == WVL_OK && err == hipSuccess; ++r)
+      status = hpsi_sequence(p, st, c, (const double*)V, 1.0, 1.0, out, nullptr, ed, ed + 1,
+                             nullptr, ws);
+    if (status != WVL_OK) break;
+    if (err == hipSuccess) err = hipEventRecord(t1, st);
+    if (err == hipSuccess) err = hipEventSynchronize(t1);
+    float ms = 0.0f;
+    if (err == hipSuccess) err = hipEventElapsedTime(&ms, t0, t1);
+    if (err != hipSuccess) { status = hipfail(err, "autotune timing"); break; }
+    p->tune_ms[k] = ms / kReps;
+    if (best < 0 || p->tune_ms[k] < best_ms) { best = k; best_ms = p->tune_ms[k]; }
+  }
+  if (best >= 0 && status == WVL_OK) {
+    p->use_xy = cands[best].xy;
+    p->xy_occ = cands[best].occ;
+    p->xy_engine = cands[best].engine;
+  } else {
+    p->use_xy = keep.xy;
+    p->xy_occ = keep.occ;
+    p->xy_engine = keep.engine;
+  }
+  p->variant = p->use_xy ? 1 + p->xy_engine : 0;
+  if (st) (void)hipStreamSynchronize(st);
+  if (t0) (void)hipEventDestroy(t0);
+  if (t1) (void)hipEventDestroy(t1);
+  if (st) (void)hipStreamDestroy(st);
+  for (void* q : {c, out, ws, V, e})
+    if (q) (void)hipFree(q);
+  return status;
 }
 
 }  // namespace

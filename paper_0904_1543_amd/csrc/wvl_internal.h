@@ -103,11 +103,21 @@ struct OrbDev {
 };
 
 // Tiling of one kind of pass: tile t of the launch belongs to the orbital b
-// with prefix[b] <= t < prefix[b+1].
+// with prefix[b] <= t < prefix[b+1].  Persistent launches (queue != nullptr)
+// run `grid` workgroups that take tiles from a work queue (an int counter,
+// zero before the launch) until all ntiles are done, in the order of
+// `order`: the prefix over the orbitals perm[0], perm[1], ... listed by
+// decreasing cost per tile, so the largest tiles start first and the small
+// ones fill the end (longest-processing-time-first list scheduling).
 struct PassGeom {
   const OrbDev* orbs;
   const int32_t* prefix;
   int32_t norb;
+  const int32_t* order;
+  const int32_t* perm;
+  int32_t* queue;
+  int32_t ntiles;
+  int32_t grid;
 };
 
 constexpr int kThreads = 256;          // threads per workgroup for the pass kernels
@@ -122,6 +132,33 @@ __device__ __forceinline__ void find_tile(const int32_t* prefix, int norb, int t
   }
   b = lo;
   t = tile - __ldg(prefix + lo);
+}
+
+// Runs body(b, t, slot) for every tile of the workgroup: the tile of its own
+// index, or (persistent launch) tiles from the queue until it runs dry.  slot
+// is the tile's index in `prefix` order (where per-tile partial sums go).
+// Every thread of the workgroup takes the same path, so body may use
+// barriers; every workgroup leaves once the counter has passed ntiles.
+template <typename F>
+__device__ __forceinline__ void for_each_tile(const PassGeom& g, F&& body) {
+  if (g.queue == nullptr) {
+    int b, t;
+    find_tile(g.prefix, g.norb, blockIdx.x, b, t);
+    body(b, t, (int)blockIdx.x);
+    return;
+  }
+  __shared__ int s_tile;
+  for (;;) {
+    __syncthreads();   // the previous tile is finished and s_tile has been read
+    if (threadIdx.x == 0) s_tile = atomicAdd(g.queue, 1);
+    __syncthreads();
+    const int vt = s_tile;
+    if (vt >= g.ntiles) break;
+    int r, t;
+    find_tile(g.order, g.norb, vt, r, t);
+    const int b = __ldg(g.perm + r);
+    body(b, t, __ldg(g.prefix + b) + t);
+  }
 }
 
 __device__ __forceinline__ int wrapi(int i, int m) {

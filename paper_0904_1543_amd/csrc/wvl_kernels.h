@@ -65,6 +65,7 @@ hipError_t launch_convert(const void* src, int sp, void* dst, int dp, int64_t n,
 // Fill with a float64 value (used instead of memset nodes so that sequences
 // can be captured in graphs).
 hipError_t launch_fill(double* dst, int64_t n, double v, hipStream_t st);
+hipError_t launch_fill_int(int32_t* dst, int n, hipStream_t st);
 
 // In-plane part of the local Hamiltonian (one z-plane per workgroup):
 // psi = W_x W_y u, rho/e_pot, t = W_y^T W_x^T (pot_scale V psi),
@@ -89,6 +90,12 @@ struct XyArgs {
   int32_t occupancy;     // waves per SIMD the kernel is compiled for (2 or 4)
   int32_t slot;          // shared: orbital g * G + slot of every group g
   int32_t engine;        // 0: vector FMA passes, 1: float64 matrix-core passes
+  // persistent launch of the unshared path (queue != nullptr): planes taken
+  // from the queue in the order of `order` (prefix of planes over perm)
+  const int32_t* order;
+  const int32_t* perm;
+  int32_t* queue;
+  int32_t ntiles;
 };
 // engine: the float64 matrix-core form of the in-plane passes
 bool xy_matrix_engine(int prec, int m1, int m2);

@@ -11,10 +11,12 @@
 //    every row of loads and stores is a coalesced 64-lane access, and each lane
 //    runs a register sliding window down its line (no LDS needed);
 //  * passes along axis 1 (the contiguous axis) stage a block of whole rows in
-//    LDS with a periodic halo of 16 values on each side, then every lane
+//    LDS with a periodic halo of 32 values on each side, then every lane
 //    computes two neighbouring outputs from a register window read from LDS.
 // The periodic boundary (Sec. 3.1) is applied by modular indexing on the
 // loads, so lines shorter than the filter are handled as well.
+
+#include <algorithm>
 
 #include "wvl_internal.h"
 #include "wvl_kernels.h"
@@ -48,8 +50,7 @@ __global__ __launch_bounds__(kThreads) void k_strided(PassGeom g, const void* __
   using T = Prec<P>;
   using V = typename T::V;
   constexpr int OLO = OpWin<OP>::OLO, OHI = OpWin<OP>::OHI, W = OHI - OLO + 1;
-  int b, t;
-  find_tile(g.prefix, g.norb, blockIdx.x, b, t);
+  for_each_tile(g, [&](int b, int t, int slot) {
   const OrbDev od = g.orbs[b];
   const int m1 = od.m[0], m2 = od.m[1], m3 = od.m[2];
   const int m = AXIS == 3 ? m3 : m2;
@@ -87,7 +88,8 @@ __global__ __launch_bounds__(kThreads) void k_strided(PassGeom g, const void* __
       for (int i = 0; i < W - 1; ++i) win[i] = win[i + 2];
     }
   }
-  if (EN) block_sum_store(e, epart + blockIdx.x);
+  if (EN) block_sum_store(e, epart + slot);
+  });
 }
 
 // ---------------------------------------------------------------------------
@@ -102,8 +104,7 @@ __global__ __launch_bounds__(kThreads) void k_contig(PassGeom g, const void* in,
   constexpr int OLO = OpWin<OP>::OLO, OHI = OpWin<OP>::OHI, W = OHI - OLO + 1;
   static_assert(OHI <= kHalo && -OLO <= kHalo, "halo too small");
   __shared__ V lds[kContigLds];
-  int b, t;
-  find_tile(g.prefix, g.norb, blockIdx.x, b, t);
+  for_each_tile(g, [&](int b, int t, int slot) {
   const OrbDev od = g.orbs[b];
   const int m1 = od.m[0];
   const int rows = od.m[1] * od.m[2];
@@ -147,7 +148,8 @@ __global__ __launch_bounds__(kThreads) void k_contig(PassGeom g, const void* in,
     T::st(out, i0, plane, y0);
     T::st(out, i0 + 1, plane, y1);
   }
-  if (EN) block_sum_store(en, epart + blockIdx.x);
+  if (EN) block_sum_store(en, epart + slot);
+  });
 }
 
 // ---------------------------------------------------------------------------
@@ -158,7 +160,7 @@ static hipError_t launch_axis(int axis, const PassGeom& g, int ntiles, const voi
                               const void* k0, int64_t plane, double kmul, double* epart,
                               hipStream_t st) {
   const bool en = epart != nullptr;
-  dim3 grid(ntiles), block(kThreads);
+  dim3 grid(g.queue ? std::min(ntiles, g.grid) : ntiles), block(kThreads);
   if (ntiles == 0) return hipSuccess;
 #define WVL_L(KERN) hipLaunchKernelGGL((KERN), grid, block, 0, st, g, in, out, k0, plane, kmul, epart)
   if (axis == 1) {

@@ -144,6 +144,11 @@ __global__ void k_fill(double* dst, int64_t n, double v) {
     dst[i] = v;
 }
 
+// work-queue counters: a kernel (not a memset) so it can sit in a captured graph
+__global__ void k_fill_int(int32_t* dst, int n) {
+  if ((int)threadIdx.x < n) dst[threadIdx.x] = 0;
+}
+
 // ---------------------------------------------------------------------------
 template <int P>
 static hipError_t pot_shared_p(const OrbDev* orbs, int norb, int64_t M, const void* psi, void* y,
@@ -212,6 +217,12 @@ hipError_t launch_fill(double* dst, int64_t n, double v, hipStream_t st) {
   int64_t blocks = (n + 255) / 256;
   if (blocks > 65536) blocks = 65536;
   hipLaunchKernelGGL(k_fill, dim3((unsigned)blocks), dim3(256), 0, st, dst, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_int(int32_t* dst, int n, hipStream_t st) {
+  if (n <= 0 || n > 256) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(256), 0, st, dst, n);
   return hipGetLastError();
 }
 

@@ -459,16 +459,16 @@ __device__ __forceinline__ void xy_orbital_plane(const XyArgs& a, int b, int z, 
 template <int P, typename E, bool SHARED, int WPE>
 __global__ __launch_bounds__(kXyThreads) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
 void k_xy(XyArgs a) {
-  int b, z, g = 0;
   if (SHARED) {
-    g = blockIdx.x % a.ngroups;
-    z = blockIdx.x / a.ngroups;
-    b = g * a.G + a.slot;
+    const int g = blockIdx.x % a.ngroups;
+    const int z = blockIdx.x / a.ngroups;
+    const int b = g * a.G + a.slot;
     if (b >= a.norb) return;
+    xy_orbital_plane<P, E, SHARED>(a, b, z, g, a.slot);
   } else {
-    find_tile(a.pq, a.norb, blockIdx.x, b, z);
+    const PassGeom geo{a.orbs, a.pq, a.norb, a.order, a.perm, a.queue, a.ntiles, 0};
+    for_each_tile(geo, [&](int b, int z, int) { xy_orbital_plane<P, E, SHARED>(a, b, z, 0, 0); });
   }
-  xy_orbital_plane<P, E, SHARED>(a, b, z, g, a.slot);
 }
 
 // rho[r] = sum_g rho_part[g][r] (group order), and per-block sums of V rho
