@@ -8,17 +8,23 @@ Sec. 2.5 and the float64 energy reductions), then the float64 overlap matrix
 and the Cholesky orthonormalisation of the batch (Sec. 5 step VIII).
 
 Workload: 256 orbitals on a periodic coarse grid of 48^3 (fine 96^3), the
-precision form of the paper's method; float64 is the headline, plain float32
-and compensated float32 (hi + lo planes) are reported beside it with their
+precision form of the method; float64 is the headline, plain float32 and
+compensated float32 (hi + lo planes) are reported beside it with their
 measured errors against the float64 oracle.  Inputs are seeded and synthetic
-and already resident in device memory when the timed region starts.
+and already resident in device memory when the timed region starts.  The
+uneven batch (512 orbitals, coarse dims uniform in 16..64 per axis, one
+potential per orbital, compensated float32, persistent launches replayed from
+a hipGraph, launch sequence picked by the tuner) is measured after it.
 
 Prints one JSON line.  Options: --steps K --warmup W --gpus 1.
 """
 
 import argparse
+import ctypes
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -27,40 +33,72 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-METRIC = ("orbital-gridpoints/s for local H*psi (HBM GB/s % peak), FP64 vs FP32-comp at 1e-10")
+METRIC = "orbital-gridpoints/s for local H*psi (HBM GB/s % peak), FP64 vs FP32-comp at 1e-10"
 HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6      # MI355X float64, vector and matrix cores alike
 ESIZE = {"f64": 8, "f32": 4, "f32c": 8}
 TOL = {"f64": 1e-12, "f32": 2e-6, "f32c": 1e-10}
 
+# Operation count of the method per orbital-gridpoint and axis (flop): the
+# 16-tap synthesis, magic filter, its transpose and analysis (16 FMA each)
+# and the 29-tap kinetic filter plus its accumulation (59 flop).
+FLOP_AXIS = 4 * 32 + 59
+FLOP_POINTWISE = 4           # rho += f psi^2, V psi
 
-def algorithmic_bytes(stage, plan, variant):
-    """Bytes a launch of `stage` must move for the whole batch (each value
-    read or written once): a 1D pass reads its input and writes its output;
-    passes that accumulate (kinetic K_{p-1}, and with the plane kernel the last
-    two z passes) also read the accumulator; the plane kernel reads u and c
-    and writes t and kxy; the potential stage reads psi, V and writes y and
-    rho; the overlap reads the coefficients once."""
-    E, es, M = plan.elems, ESIZE[plan.prec], plan.M[0]
+
+def stage_model(stage, prec, variant):
+    """(bound, algorithmic bytes per orbital-gridpoint, algorithmic flop per
+    orbital-gridpoint) of one profiled stage.  Bytes: each value the stage
+    must read or write once (plane kernel: u and c in, t and kxy out; a z
+    pass that accumulates also reads the accumulator); flop: the method's
+    operation count for the axes the stage covers."""
+    es = ESIZE[prec]
     if stage == "xy_plane":
-        return 4 * E * es
-    if stage in ("ck_z", "cwt_z") and variant == 1:
-        return 3 * E * es
-    if stage.startswith("kin_") or stage.startswith("ck_"):
-        return 3 * E * es
+        bound = "mfma" if (prec == "f64" and variant == 2) else "alu"
+        return bound, 4 * es, 2 * FLOP_AXIS + FLOP_POINTWISE
+    if stage.endswith("_z") and stage.startswith(("ck", "cwt")) and variant >= 1:
+        return "hbm", 3 * es, None
+    if stage.startswith(("kin_", "ck_")):
+        return "hbm", 3 * es, None
     if stage[:3] in ("mf_", "mft", "syn", "ana", "cw_", "cwt"):
-        return 2 * E * es
+        return "hbm", 2 * es, None
     if stage == "potential":
-        return 2 * E * es + 2 * M * 8
-    if stage in ("overlap",):
-        return E * es
-    if stage == "trmm":
-        return 2 * E * es
-    return None
+        return "hbm", 2 * es, None
+    if stage in ("overlap", "trmm"):
+        return "mfma", None, None
+    return None, None, None
+
+
+def kernel_sources_hash():
+    """Hash of the HIP sources: a stored counter reading is only used while
+    the kernels are the ones it was taken on."""
+    h = hashlib.sha256()
+    cdir = os.path.join(ROOT, "paper_0904_1543_amd", "csrc")
+    for name in sorted(os.listdir(cdir)):
+        if name.endswith((".hip", ".h")):
+            with open(os.path.join(cdir, name), "rb") as f:
+                h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()[:16]
+
+
+def stored_traffic(stage):
+    """HBM bytes per launch of `stage` from the committed counter summary
+    (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel calibration), or None
+    if there is none for the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"{stage}_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m = re.search(r"^sources_hash:\s*(\S+)", text, re.M)
+    b = re.search(r"^hbm_bytes_per_launch:\s*([0-9.eE+]+)", text, re.M)
+    if not m or not b or m.group(1) != kernel_sources_hash():
+        return None
+    return float(b.group(1))
 
 
 def run_precision(prec, C, V, dims, steps, warmup, sample_orbs):
     import torch
-    from paper_0904_1543_amd import ops
+    from paper_0904_1543_amd import lib, ops
 
     plan = ops.Plan(dims, prec=prec)
     c = plan.pack(C)
@@ -69,9 +107,6 @@ def run_precision(prec, C, V, dims, steps, warmup, sample_orbs):
     rho = torch.empty(plan.M[0], dtype=torch.float64, device=plan.dev)
     en = torch.empty(2, dtype=torch.float64, device=plan.dev)
     eorb = torch.empty(2 * plan.norb, dtype=torch.float64, device=plan.dev)
-
-    import ctypes
-    from paper_0904_1543_amd import lib
 
     def hpsi():
         lib.wvl_local_hpsi(plan.h, ops.ptr(c), ops.ptr(Vt), 1.0, 1.0, ops.ptr(out), ops.ptr(rho),
@@ -110,14 +145,15 @@ def run_precision(prec, C, V, dims, steps, warmup, sample_orbs):
     recs = plan.profile_read()
     plan.profile(0)
     plan.sync()
-    # per-stage launch durations over the timed region
+    # per-stage launch durations over the timed region (hipEvents on the
+    # launches' own stream)
     stages = {}
     for name, t in recs:
         s = stages.setdefault(name, [0.0, 0])
         s[0] += t
         s[1] += 1
-    table = {k: {"avg_ms": v[0] / v[1], "launches": v[1], "share": v[0] / (ms * steps)}
-             for k, v in stages.items()}
+    table = {k: {"avg_ms": v[0] / v[1], "launches": v[1], "per_step": v[1] / steps,
+                 "total_ms_per_step": v[0] / steps} for k, v in stages.items()}
     hpsi_ms = sum(v[0] for k, v in stages.items()
                   if k not in ("overlap", "cholesky", "trmm")) / steps
     v = ctypes.c_int32()
@@ -126,6 +162,54 @@ def run_precision(prec, C, V, dims, steps, warmup, sample_orbs):
                energies=energies, variant=v.value)
     del c, Vt, out, rho
     return res
+
+
+def run_uneven(steps, warmup):
+    """The 512-orbital uneven batch, compensated float32, persistent launches
+    in a replayed hipGraph, launch sequence chosen by the tuner."""
+    import torch
+    from paper_0904_1543_amd import inputs, lib, ops
+
+    wl = inputs.workload(5)
+    dims = wl["dims"]
+    t = time.perf_counter()
+    plan = ops.Plan(dims, prec="f32c", shared_v=False, persistent=True, graph=True,
+                    autotune=True)
+    tune_s = time.perf_counter() - t
+    c = plan.pack(wl["C"])
+    Vt = plan.pack_potential(wl["V"])
+    del wl
+    out = plan.empty()
+    eorb = torch.empty(2 * plan.norb, dtype=torch.float64, device=plan.dev)
+
+    def hpsi():
+        lib.wvl_local_hpsi(plan.h, ops.ptr(c), ops.ptr(Vt), 1.0, 1.0, ops.ptr(out), None, None,
+                           None, ops.ptr(eorb), ops.ptr(plan.ws), ops.stream_handle())
+
+    for _ in range(max(warmup, 1)):
+        hpsi()
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(steps):
+        hpsi()
+    t1.record()
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / steps
+    v = ctypes.c_int32()
+    tm = (ctypes.c_double * 4)()
+    lib.wvl_plan_tuning(plan.h, ctypes.byref(v), tm, 4)
+    pts = int(sum(np.prod(inputs.fine_shape(d)) for d in dims))
+    names = ["pass_by_pass", "plane_occ4", "plane_occ2", "plane_vector_engine"]
+    return {"workload": "512 orbitals, coarse dims uniform in 16..64 per axis (seed 5), "
+                        "one 16-Gaussian potential per orbital, compensated float32, "
+                        "persistent launches replayed from a hipGraph",
+            "orbital_gridpoints": pts, "ms_per_hpsi": ms,
+            "orbital_gridpoints_per_s": pts / (ms * 1e-3),
+            "variant": v.value,
+            "tuner_ms": {names[i]: (tm[i] if tm[i] >= 0 else None) for i in range(4)},
+            "tuning_s": tune_s}
 
 
 def main():
@@ -137,10 +221,11 @@ def main():
     ap.add_argument("--cpu-orbitals", type=int, default=40,
                     help="orbitals of the batch the oracle is timed on")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-uneven", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              "(the orbital batch would be split across GPUs, see the design notes)",
+              "(the orbital batch would be split across GPUs by orbitals, see the design notes)",
               file=sys.stderr)
         sys.exit(2)
 
@@ -148,6 +233,14 @@ def main():
     from paper_0904_1543_amd import inputs
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    # known-size copy before the measured work: the counter runs of the
+    # profiles calibrate FETCH_SIZE / WRITE_SIZE against it (2 x 1 GiB moved)
+    src = torch.ones(1 << 27, dtype=torch.float64, device="cuda:0")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+
     wl = inputs.workload(3)
     C, V, dims = wl["C"], wl["V"], wl["dims"]
     norb = len(dims)
@@ -162,10 +255,19 @@ def main():
         results[prec] = run_precision(prec, C, V, dims, args.steps, args.warmup, sample)
         torch.cuda.empty_cache()
 
+    uneven = None
+    if not args.no_uneven:
+        print("[bench] uneven batch: 512 orbitals, f32c, persistent + graph + tuner",
+              file=sys.stderr, flush=True)
+        uneven = run_uneven(args.steps, args.warmup)
+        torch.cuda.empty_cache()
+
     # oracle: CPU baseline on a bounded sample, and the errors of every precision
     cpu = None
     errors = {}
     if not args.no_cpu_baseline:
+        print(f"[bench] oracle on {args.cpu_orbitals} orbitals (one host thread)", file=sys.stderr,
+              flush=True)
         from oracle import wavelet as W
         ncpu = max(1, min(args.cpu_orbitals, norb))
         idx = sorted(set([0, norb - 1] + list(range(1, ncpu - 1))))[:ncpu]
@@ -176,8 +278,9 @@ def main():
         tcpu = time.perf_counter() - t
         cpu = {"value": len(idx) * pts / norb / tcpu, "unit": "orbital-gridpoints/s",
                "cores": 1, "kind": "oracle",
-               "sample": f"{len(idx)} of {norb} orbitals (96^3 fine grid each), plain float64 "
-                         f"numpy oracle, single thread, {tcpu:.1f} s"}
+               "sample": f"local H*psi of {len(idx)} of the {norb} orbitals (fine 96^3 each), "
+                         f"plain float64 numpy oracle on one host thread, {tcpu:.1f} s; the "
+                         "overlap/Cholesky step is not in the sample"}
         for prec, r in results.items():
             num = sum(np.sum((r["got"][b] - refs[b]) ** 2) for b in r["got"])
             den = sum(np.sum(refs[b] ** 2) for b in r["got"])
@@ -186,16 +289,29 @@ def main():
     head = "f64" if "f64" in results else precs[0]
     r = results[head]
     ms = r["ms_per_step"]
-    # dominant kernel of the headline precision
-    dom, dstat = max(r["stages"].items(), key=lambda kv: kv[1]["avg_ms"] * kv[1]["launches"])
-    ab = algorithmic_bytes(dom, r["plan"], r["variant"])
+    # dominant kernel of the headline precision, per launch
+    dom, dstat = max(r["stages"].items(), key=lambda kv: kv[1]["total_ms_per_step"])
+    bound, bpp, fpp = stage_model(dom, head, r["variant"])
     roof = None
-    if ab is not None:
-        gbs = ab / (dstat["avg_ms"] * 1e-3) / 1e9
-        roof = {"bound": "hbm", "kernel": dom, "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
-                "avg_ms": round(dstat["avg_ms"], 4),
-                "algorithmic_bytes": int(ab)}
+    if bound is not None:
+        units = pts / dstat["per_step"]            # orbital-gridpoints per launch
+        sec = dstat["avg_ms"] * 1e-3
+        traffic = stored_traffic(dom)
+        if bound == "hbm" and bpp is not None:
+            ach = units * bpp / sec / 1e9
+            roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4)}
+        elif fpp is not None:
+            ach = units * fpp / sec / 1e12
+            roof = {"bound": bound, "achieved": round(ach, 2), "peak": FP64_PEAK_TFLOPS,
+                    "unit": "TFLOP/s", "frac": round(ach / FP64_PEAK_TFLOPS, 4)}
+        if roof is not None:
+            roof.update({"traffic": traffic, "kernel": dom, "avg_launch_ms": round(dstat["avg_ms"], 4),
+                         "launches_per_step": dstat["per_step"],
+                         "orbital_gridpoints_per_launch": int(units),
+                         "algorithmic_bytes_per_launch": int(units * bpp) if bpp else None,
+                         "algorithmic_flop_per_launch": int(units * fpp) if fpp else None,
+                         "hbm_equivalent_GBps": round(units * bpp / sec / 1e9, 1) if bpp else None})
     line = {
         "metric": METRIC,
         "value": pts / (ms * 1e-3),
@@ -218,17 +334,19 @@ def main():
         "cpu_baseline": cpu,
         "precisions": {
             p: {"ms_per_step": v["ms_per_step"],
-                "hpsi_variant": "plane-resident" if v["variant"] == 1 else "pass-by-pass",
+                "hpsi_variant": {0: "pass-by-pass", 1: "plane-resident (vector FMA)",
+                                 2: "plane-resident (float64 matrix cores)"}[v["variant"]],
                 "orbital_gridpoints_per_s": pts / (v["ms_per_step"] * 1e-3),
                 "hpsi_ms": v["hpsi_ms"],
                 "hpsi_orbital_gridpoints_per_s": pts / (v["hpsi_ms"] * 1e-3),
                 "rel_err_vs_oracle": errors.get(p),
                 "tolerance": TOL[p],
                 "e_loc": float(v["energies"][0]), "e_kin": float(v["energies"][1]),
-                "stages": {k: {"avg_ms": round(s["avg_ms"], 4), "launches": s["launches"]}
+                "stages": {k: {"avg_ms": round(s["avg_ms"], 4), "per_step": s["per_step"]}
                            for k, s in sorted(v["stages"].items(),
-                                              key=lambda kv: -kv[1]["avg_ms"] * kv[1]["launches"])}}
+                                              key=lambda kv: -kv[1]["total_ms_per_step"])}}
             for p, v in results.items()},
+        "uneven_batch": uneven,
     }
     print(json.dumps(line))
 

@@ -540,7 +540,6 @@ int hpsi_sequence(wvl_plan* p, hipStream_t st, const void* c, const double* V, d
     }
     WVL_CHK(q.pass(OP_CW, 3, c, A));
     {
-      Mark mk(p, st, ST_XY);
       XyArgs xa;
       xa.orbs = p->d_orbs;
       xa.pq = p->d_pq;
@@ -577,10 +576,12 @@ int hpsi_sequence(wvl_plan* p, hipStream_t st, const void* c, const double* V, d
       }
       if (p->shared) {
         for (int slot = 0; slot < p->xy_G; ++slot) {
+          Mark mk(p, st, ST_XY);
           xa.slot = slot;
           WVL_CHK(launch_xy(p->prec, xa, p->xy_m1, p->xy_m2, p->xy_blocks, st));
         }
       } else {
+        Mark mk(p, st, ST_XY);
         xa.slot = 0;
         WVL_CHK(launch_xy(p->prec, xa, p->xy_m1, p->xy_m2, nblocks, st));
       }
