@@ -170,49 +170,67 @@ constexpr int kCb = 64;
 // zeroed), inv(L_JJ) to D (leading dimension ldd).  info[0] = first bad pivot + 1.
 __global__ __launch_bounds__(256) void k_potrf_block(double* A, int lda, int r0, int b, double* D,
                                                      int ldd, int* info) {
-  __shared__ double a[kCb][kCb];
-  __shared__ double m[kCb][kCb];
+  // LDS: a (the block, factorised in place) and m (its inverse), rows padded
+  // to an odd pitch so that a column read by 64 lanes hits distinct banks.
+  // Thread t owns row r = t mod 64 and the 16 columns of quarter t / 64.
+  extern __shared__ double lds_potrf[];
+  constexpr int P = kCb + 1;
+  double* a = lds_potrf;
+  double* m = lds_potrf + kCb * P;
   const int t = threadIdx.x;
-  for (int e = t; e < b * b; e += 256) {
-    const int i = e / b, k = e % b;
-    a[i][k] = A[(int64_t)(r0 + i) * lda + r0 + k];
-    m[i][k] = (i == k) ? 1.0 : 0.0;
+  const int r = t & 63, cq = t >> 6;
+  for (int kk = 0; kk < 16; ++kk) {
+    const int k = cq * 16 + kk;
+    const bool in = r < b && k < b;
+    a[r * P + k] = in ? A[(int64_t)(r0 + r) * lda + r0 + k] : (r == k ? 1.0 : 0.0);
+    m[r * P + k] = (r == k) ? 1.0 : 0.0;
   }
   __syncthreads();
-  // right-looking unblocked Cholesky in LDS
+  // right-looking unblocked Cholesky
   for (int j = 0; j < b; ++j) {
-    double d = a[j][j];
+    double d = a[j * P + j];
     if (!(d > 0.0)) {
       if (t == 0 && info[0] == 0) info[0] = r0 + j + 1;
       d = 1.0;
     }
     const double l = sqrt(d);
+    __syncthreads();   // every thread has read the pivot
+    if (cq == 0 && r > j && r < b) a[r * P + j] /= l;
+    if (t == 0) a[j * P + j] = l;
     __syncthreads();
-    if (t == 0) a[j][j] = l;
-    for (int i = j + 1 + t; i < b; i += 256) a[i][j] /= l;
-    __syncthreads();
-    for (int e = t; e < b * b; e += 256) {
-      const int i = e / b, k = e % b;
-      if (k > j && k <= i) a[i][k] -= a[i][j] * a[k][j];
+    if (r > j && r < b) {
+      const double lr = a[r * P + j];
+      #pragma unroll
+      for (int kk = 0; kk < 16; ++kk) {
+        const int k = cq * 16 + kk;
+        if (k > j && k <= r) a[r * P + k] -= lr * a[k * P + j];
+      }
     }
     __syncthreads();
   }
   // inverse by forward elimination on [L | I]
   for (int j = 0; j < b; ++j) {
-    const double inv = 1.0 / a[j][j];
+    const double inv = 1.0 / a[j * P + j];
+    if (t <= j) m[j * P + t] *= inv;
     __syncthreads();
-    for (int k = t; k <= j; k += 256) m[j][k] *= inv;
-    __syncthreads();
-    for (int e = t; e < b * b; e += 256) {
-      const int i = e / b, k = e % b;
-      if (i > j && k <= j) m[i][k] -= a[i][j] * m[j][k];
+    if (r > j && r < b) {
+      const double lr = a[r * P + j];
+      #pragma unroll
+      for (int kk = 0; kk < 16; ++kk) {
+        const int k = cq * 16 + kk;
+        if (k <= j) m[r * P + k] -= lr * m[j * P + k];
+      }
     }
     __syncthreads();
   }
-  for (int e = t; e < b * b; e += 256) {
-    const int i = e / b, k = e % b;
-    A[(int64_t)(r0 + i) * lda + r0 + k] = (k <= i) ? a[i][k] : 0.0;
-    D[(int64_t)i * ldd + k] = (k <= i) ? m[i][k] : 0.0;
+  if (r < b) {
+    for (int kk = 0; kk < 16; ++kk) {
+      const int k = cq * 16 + kk;
+      if (k < b) {
+        A[(int64_t)(r0 + r) * lda + r0 + k] = (k <= r) ? a[r * P + k] : 0.0;
+        D[(int64_t)r * ldd + k] = (k <= r) ? m[r * P + k] : 0.0;
+      }
+    }
   }
 }
 
@@ -266,7 +284,8 @@ hipError_t launch_cholesky_inv(double* S, double* Linv, double* T, int n, int* i
   for (int J = 0; J < nb; ++J) {
     const int r0 = J * kCb, b = min(kCb, n - r0);
     double* DJ = Linv + (int64_t)r0 * n + r0;
-    hipLaunchKernelGGL(k_potrf_block, dim3(1), dim3(256), 0, st, S, n, r0, b, DJ, n, info);
+    hipLaunchKernelGGL(k_potrf_block, dim3(1), dim3(256), 2 * kCb * (kCb + 1) * sizeof(double), st,
+                       S, n, r0, b, DJ, n, info);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     const int r1 = r0 + b, rem = n - r1;
     if (rem <= 0) break;

@@ -23,6 +23,8 @@
 
 namespace wvl {
 
+constexpr int kPf = 4;   // output pairs whose loads are in flight (strided passes)
+
 template <int P, int OP>
 __device__ __forceinline__ void pair_conv(const typename Prec<P>::V* win, typename Prec<P>::V& y0,
                                           typename Prec<P>::V& y1) {
@@ -65,27 +67,60 @@ __global__ __launch_bounds__(kThreads) void k_strided(PassGeom g, const void* __
     V win[W + 1];
     #pragma unroll
     for (int i = 0; i < W - 1; ++i) win[i] = T::ldc(in, base + (int64_t)wrapi(i - OHI, m) * stride, plane);
-    for (int k = 0; k < m; k += 2) {
-      win[W - 1] = T::ldc(in, base + (int64_t)wrapi(k - OLO, m) * stride, plane);
-      win[W] = T::ldc(in, base + (int64_t)wrapi(k + 1 - OLO, m) * stride, plane);
-      V y0, y1;
-      pair_conv<P, OP>(win, y0, y1);
-      if (OP == OP_KIN || OP == OP_CK) {
-        // energies use the unweighted operator; kmul weights the output only
-        y0 = T::scale(y0, ks);
-        y1 = T::scale(y1, ks);
-        if (EN) e += T::d(win[OHI]) * T::d(y0) + T::d(win[OHI + 1]) * T::d(y1);
-        if (kmul != 1.0) { y0 = T::scale(y0, kmul); y1 = T::scale(y1, kmul); }
+    // The loads of the next kPf output pairs are in flight while a pair is
+    // computed (ring of registers, refilled as it is consumed): a wave keeps
+    // 2 kPf input loads (and as many accumulator loads) outstanding.
+    V q0[kPf], q1[kPf], a0[kPf], a1[kPf];
+    #pragma unroll
+    for (int d = 0; d < kPf; ++d) {
+      const int kk = 2 * d;
+      if (kk < m) {
+        q0[d] = T::ldc(in, base + (int64_t)wrapi(kk - OLO, m) * stride, plane);
+        q1[d] = T::ldc(in, base + (int64_t)wrapi(kk + 1 - OLO, m) * stride, plane);
+        if (K0) {
+          a0[d] = T::ldc(k0, base + (int64_t)kk * stride, plane);
+          a1[d] = T::ldc(k0, base + (int64_t)(kk + 1) * stride, plane);
+        }
       }
-      const int64_t i0 = base + (int64_t)k * stride, i1 = i0 + stride;
-      if (K0) {
-        y0 = T::plus(y0, T::ldc(k0, i0, plane));
-        y1 = T::plus(y1, T::ldc(k0, i1, plane));
-      }
-      T::st(out, i0, plane, y0);
-      T::st(out, i1, plane, y1);
+    }
+    for (int k = 0; k < m; k += 2 * kPf) {
       #pragma unroll
-      for (int i = 0; i < W - 1; ++i) win[i] = win[i + 2];
+      for (int d = 0; d < kPf; ++d) {
+        const int kk = k + 2 * d;    // m is even: a pair never straddles the end
+        if (kk < m) {
+          win[W - 1] = q0[d];
+          win[W] = q1[d];
+          V c0, c1;
+          if (K0) { c0 = a0[d]; c1 = a1[d]; }
+          const int kn = kk + 2 * kPf;
+          if (kn < m) {
+            q0[d] = T::ldc(in, base + (int64_t)wrapi(kn - OLO, m) * stride, plane);
+            q1[d] = T::ldc(in, base + (int64_t)wrapi(kn + 1 - OLO, m) * stride, plane);
+            if (K0) {
+              a0[d] = T::ldc(k0, base + (int64_t)kn * stride, plane);
+              a1[d] = T::ldc(k0, base + (int64_t)(kn + 1) * stride, plane);
+            }
+          }
+          V y0, y1;
+          pair_conv<P, OP>(win, y0, y1);
+          if (OP == OP_KIN || OP == OP_CK) {
+            // energies use the unweighted operator; kmul weights the output only
+            y0 = T::scale(y0, ks);
+            y1 = T::scale(y1, ks);
+            if (EN) e += T::d(win[OHI]) * T::d(y0) + T::d(win[OHI + 1]) * T::d(y1);
+            if (kmul != 1.0) { y0 = T::scale(y0, kmul); y1 = T::scale(y1, kmul); }
+          }
+          const int64_t i0 = base + (int64_t)kk * stride, i1 = i0 + stride;
+          if (K0) {
+            y0 = T::plus(y0, c0);
+            y1 = T::plus(y1, c1);
+          }
+          T::st(out, i0, plane, y0);
+          T::st(out, i1, plane, y1);
+          #pragma unroll
+          for (int i = 0; i < W - 1; ++i) win[i] = win[i + 2];
+        }
+      }
     }
   }
   if (EN) block_sum_store(e, epart + slot);
