@@ -574,7 +574,13 @@ int hpsi_sequence(wvl_plan* p, hipStream_t st, const void* c, const double* V, d
         const int per_cu = std::max(1, std::min(p->xy_occ / 2, (int)(p->ctx->lds_per_block / lds)));
         nblocks = std::min(nblocks, std::max(1, p->ctx->cus) * per_cu);
       }
-      if (p->shared) {
+      if (p->shared && p->xy_engine) {
+        // matrix-core engine: one launch, each workgroup runs its group's
+        // orbitals in turn
+        Mark mk(p, st, ST_XY);
+        xa.slot = -1;
+        WVL_CHK(launch_xy(p->prec, xa, p->xy_m1, p->xy_m2, p->xy_blocks, st));
+      } else if (p->shared) {
         for (int slot = 0; slot < p->xy_G; ++slot) {
           Mark mk(p, st, ST_XY);
           xa.slot = slot;

@@ -88,7 +88,7 @@ struct XyArgs {
   double* epot;          // per (orbital, plane)
   double* ekin;          // per (orbital, plane): <c, (K_x + K_y) c> over the plane
   int32_t occupancy;     // waves per SIMD the kernel is compiled for (2 or 4)
-  int32_t slot;          // shared: orbital g * G + slot of every group g
+  int32_t slot;          // shared: orbital g * G + slot of every group g; -1: all slots in turn
   int32_t engine;        // 0: vector FMA passes, 1: float64 matrix-core passes
   // persistent launch of the unshared path (queue != nullptr): planes taken
   // from the queue in the order of `order` (prefix of planes over perm)

@@ -291,6 +291,9 @@ struct MfEngine {
     const int es = AX == 1 ? 1 : pitch;
     double fc[S];
     const double* ft = frag_tab<OP>();
+    // opaque to the optimiser: the table is re-read per pass instead of being
+    // hoisted (and kept live in registers) across a loop over orbitals
+    asm volatile("" : "+s"(ft));
     #pragma unroll
     for (int s = 0; s < S; ++s) fc[s] = ft[s * 64 + lane];
     r.n = 0;
@@ -452,19 +455,31 @@ __device__ __forceinline__ void xy_orbital_plane(const XyArgs& a, int b, int z, 
   }
 }
 
-// Grid: shared-potential batches (SHARED): blockIdx.x = z * ngroups + g and
-// the orbital is g * G + slot (one launch per slot, in slot order, so the
-// group's density partial is accumulated in orbital order); otherwise one
-// (orbital, plane) per block via the plane prefix pq.
+// Grid: shared-potential batches (SHARED): blockIdx.x = z * ngroups + g; the
+// orbitals are g * G + slot, either one slot per launch (launches in slot
+// order) or, with slot < 0, all slots of the group in one workgroup, in
+// order; either way the group's density partial is accumulated in orbital
+// order.  Otherwise one (orbital, plane) per tile via the plane prefix pq.
 template <int P, typename E, bool SHARED, int WPE>
 __global__ __launch_bounds__(kXyThreads) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
 void k_xy(XyArgs a) {
   if (SHARED) {
     const int g = blockIdx.x % a.ngroups;
     const int z = blockIdx.x / a.ngroups;
-    const int b = g * a.G + a.slot;
-    if (b >= a.norb) return;
-    xy_orbital_plane<P, E, SHARED>(a, b, z, g, a.slot);
+    if (a.slot >= 0) {
+      const int b = g * a.G + a.slot;
+      if (b >= a.norb) return;
+      xy_orbital_plane<P, E, SHARED>(a, b, z, g, a.slot);
+    } else {
+      // every orbital of the group in turn: the group's density partial of
+      // this plane stays in L2 between them
+      #pragma nounroll
+      for (int slot = 0; slot < a.G; ++slot) {
+        const int b = g * a.G + slot;
+        if (b >= a.norb) break;
+        xy_orbital_plane<P, E, SHARED>(a, b, z, g, slot);
+      }
+    }
   } else {
     const PassGeom geo{a.orbs, a.pq, a.norb, a.order, a.perm, a.queue, a.ntiles, 0};
     for_each_tile(geo, [&](int b, int z, int) { xy_orbital_plane<P, E, SHARED>(a, b, z, 0, 0); });
