@@ -31,9 +31,13 @@ constexpr int kXcd = 8;         // XCDs of the MI355X
 __host__ __device__ inline int nblk64(int norb) { return (norb + kBlk - 1) / kBlk; }
 __host__ __device__ inline int ntri(int nb) { return nb * (nb + 1) / 2; }
 
+static int64_t syrk32_partials(int norb, int64_t len);
+
 int64_t syrk_partials(int norb, int64_t len) {
   const int64_t nslice = (len + kSlice - 1) / kSlice;
-  return nslice * ntri(nblk64(norb)) * kBlk * kBlk;
+  const int64_t p64 = nslice * ntri(nblk64(norb)) * kBlk * kBlk;
+  const int64_t p32 = syrk32_partials(norb, len);
+  return p64 > p32 ? p64 : p32;
 }
 
 // 4 consecutive coefficients of one row as float64 (zero outside the matrix)
@@ -130,9 +134,161 @@ __global__ void k_syrk_reduce(const double* __restrict__ part, int norb, int nsl
   S[(int64_t)j * norb + i] = s;
 }
 
+// ---------------------------------------------------------------------------
+// SYRK for up to 256 orbitals, one workgroup (8 waves) per coefficient slice.
+// Chunks of 16 coefficients of every orbital are staged in LDS (double
+// buffered: the next chunk's loads are in flight while the current one is
+// multiplied), so HBM is read once; the lower triangle of S is cut into
+// 32 x 32 blocks, dealt to the waves round-robin, each a 2 x 2 set of 16 x 16
+// matrix-core tiles.  Lane group q of step s takes coefficient 4 q + s of the
+// chunk for both operands (the sum does not depend on the order).  Slice
+// partials are summed in slice order by k_syrk32_reduce.
+// ---------------------------------------------------------------------------
+constexpr int kS32Waves = 8;
+constexpr int kS32MaxBlocks = 5;     // ceil(36 / 8) blocks per wave at 256 orbitals
+constexpr int kS32Pitch = 17;        // doubles per staged row (16 + 1: distinct banks)
+constexpr int kS32Rows = 256;
+
+__host__ __device__ inline int nblk32(int norb) { return (norb + 31) / 32; }
+
+template <int P>
+__global__ __launch_bounds__(512) void k_syrk32(const void* __restrict__ X, int64_t plane, int norb,
+                                                int64_t len, int64_t slen, double* __restrict__ part) {
+  using T = Prec<P>;
+  __shared__ double lds[2][kS32Rows * kS32Pitch];
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  const int li = lane & 15, q = lane >> 4;
+  const int nb = nblk32(norb), nt = ntri(nb);
+  const int rows = nb * 32;
+  const int64_t k0 = (int64_t)blockIdx.x * slen;
+  const int64_t k1 = min(len, k0 + slen);
+  // staging: thread -> (row, half of the 16 coefficients)
+  const int srow = tid >> 1, shalf = (tid & 1) * 8;
+  double stage[8];
+  auto fetch = [&](int64_t k) {
+    #pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int64_t kk = k + shalf + u;
+      stage[u] = (srow < norb && kk < k1) ? T::d(T::ldc(X, (int64_t)srow * len + kk, plane)) : 0.0;
+    }
+  };
+  auto put = [&](int buf) {
+    if (srow < rows) {
+      #pragma unroll
+      for (int u = 0; u < 8; ++u) lds[buf][srow * kS32Pitch + shalf + u] = stage[u];
+    }
+  };
+  // blocks of this wave: tri = w + 8 m -> (I, J), I >= J
+  int bi[kS32MaxBlocks], bj[kS32MaxBlocks];
+  #pragma unroll
+  for (int m = 0; m < kS32MaxBlocks; ++m) {
+    const int tri = w + kS32Waves * m;
+    int I = 0;
+    while ((I + 1) * (I + 2) / 2 <= tri) ++I;
+    bi[m] = I;
+    bj[m] = tri - I * (I + 1) / 2;
+  }
+  d4 acc[kS32MaxBlocks][2][2];
+  #pragma unroll
+  for (int m = 0; m < kS32MaxBlocks; ++m)
+    #pragma unroll
+    for (int a = 0; a < 2; ++a)
+      #pragma unroll
+      for (int c = 0; c < 2; ++c) acc[m][a][c] = d4{0.0, 0.0, 0.0, 0.0};
+  int buf = 0;
+  if (k0 < k1) {
+    fetch(k0);
+    put(0);
+  }
+  __syncthreads();
+  for (int64_t k = k0; k < k1; k += 16) {
+    const bool more = k + 16 < k1;
+    if (more) fetch(k + 16);                     // in flight during the products
+    const double* L = lds[buf];
+    #pragma unroll
+    for (int m = 0; m < kS32MaxBlocks; ++m) {
+      if (w + kS32Waves * m >= nt) break;
+      const int I = bi[m], J = bj[m];
+      #pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        double av[2], bv[2];
+        #pragma unroll
+        for (int a = 0; a < 2; ++a) {
+          av[a] = L[(I * 32 + a * 16 + li) * kS32Pitch + 4 * q + s];
+          bv[a] = L[(J * 32 + a * 16 + li) * kS32Pitch + 4 * q + s];
+        }
+        #pragma unroll
+        for (int a = 0; a < 2; ++a)
+          #pragma unroll
+          for (int c = 0; c < 2; ++c)
+            acc[m][a][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[c], acc[m][a][c], 0, 0, 0);
+      }
+    }
+    if (more) put(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+  }
+  // tile element (i, j) is in lane j + 16 (i mod 4), register i / 4
+  #pragma unroll
+  for (int m = 0; m < kS32MaxBlocks; ++m) {
+    const int tri = w + kS32Waves * m;
+    if (tri >= nt) break;
+    double* dst = part + ((int64_t)blockIdx.x * nt + tri) * 1024;
+    #pragma unroll
+    for (int a = 0; a < 2; ++a)
+      #pragma unroll
+      for (int c = 0; c < 2; ++c)
+        #pragma unroll
+        for (int v = 0; v < 4; ++v) dst[(a * 16 + q + 4 * v) * 32 + c * 16 + li] = acc[m][a][c][v];
+  }
+}
+
+// S[i][j] (and S[j][i]) = sum over slices, in slice order.
+__global__ void k_syrk32_reduce(const double* __restrict__ part, int norb, int nslice,
+                                double* __restrict__ S) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)norb * norb) return;
+  const int i = (int)(idx / norb), j = (int)(idx % norb);
+  if (j > i) return;
+  const int nt = ntri(nblk32(norb));
+  const int I = i / 32, J = j / 32;
+  const int tri = I * (I + 1) / 2 + J;
+  const int r = i % 32, c = j % 32;
+  double s = 0.0;
+  for (int q = 0; q < nslice; ++q) s += part[((int64_t)q * nt + tri) * 1024 + r * 32 + c];
+  S[(int64_t)i * norb + j] = s;
+  S[(int64_t)j * norb + i] = s;
+}
+
+constexpr int kS32Slices = 256;      // one workgroup per CU
+
+static int64_t syrk32_slice(int64_t len) {
+  int64_t sl = (len + kS32Slices - 1) / kS32Slices;
+  sl = (sl + 15) / 16 * 16;
+  return sl < 16 ? 16 : sl;
+}
+
+static int64_t syrk32_partials(int norb, int64_t len) {
+  if (norb > kS32Rows) return 0;
+  const int64_t sl = syrk32_slice(len);
+  return ((len + sl - 1) / sl) * ntri(nblk32(norb)) * 1024;
+}
+
 template <int P>
 static hipError_t overlap_p(const void* X, int64_t plane, int norb, int64_t len, double* S,
                             double* work, hipStream_t st) {
+  if (norb <= kS32Rows) {
+    const int64_t sl = syrk32_slice(len);
+    const int nslice = (int)((len + sl - 1) / sl);
+    hipLaunchKernelGGL((k_syrk32<P>), dim3((unsigned)nslice), dim3(512), 0, st, X, plane, norb, len,
+                       sl, work);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int64_t n2 = (int64_t)norb * norb;
+    hipLaunchKernelGGL(k_syrk32_reduce, dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, st, work,
+                       norb, nslice, S);
+    return hipGetLastError();
+  }
   const int nt = ntri(nblk64(norb));
   const int nslice = (int)((len + kSlice - 1) / kSlice);
   const int ngrp = (nslice + kXcd - 1) / kXcd;
