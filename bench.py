@@ -218,7 +218,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--precs", default="f64,f32c,f32")
-    ap.add_argument("--cpu-orbitals", type=int, default=40,
+    ap.add_argument("--cpu-orbitals", type=int, default=80,
                     help="orbitals of the batch the oracle is timed on")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-uneven", action="store_true")

@@ -6,14 +6,14 @@
 // S = L L^T and the orbitals are replaced by the rows of L^{-1} X.  The paper
 // runs the SYRK on the GPU and the factorisation on the host; here everything
 // stays on the GPU, in float64:
-//  * SYRK on the float64 matrix cores (v_mfma_f64_16x16x4f64).  One wave owns
-//    a 64x64 block of the lower triangle of S over a slice of the coefficient
-//    axis.  A matrix-core step sums over 4 coefficients; since the sum over
-//    coefficients does not depend on their order, lane group q of a step takes
-//    coefficient 4q + s of a 16-coefficient chunk for both operands, so every
-//    lane loads 4 consecutive values and each orbital row is read as whole
-//    128-byte lines.  The blocks of one slice are placed on one XCD so the
-//    slice is fetched into one L2.  Slice partials are summed in a fixed order;
+//  * SYRK on the float64 matrix cores (v_mfma_f64_16x16x4f64).  A step sums
+//    over 4 coefficients; since the sum does not depend on their order, lane
+//    group q of step s takes coefficient 4q + s of a 16-coefficient chunk for
+//    both operands.  Up to 256 orbitals, one workgroup per coefficient slice
+//    stages the chunks of all rows in LDS and its waves compute 32x32 blocks
+//    of the lower triangle; for more orbitals one wave owns a 64x64 block over
+//    a slice, reading its rows as whole 128-byte lines, with the blocks of one
+//    slice placed on one XCD.  Slice partials are summed in a fixed order;
 //  * blocked Cholesky and L^{-1} with 64 x 64 diagonal blocks factorised in
 //    LDS and small float64 products for the panels and the trailing updates;
 //  * X <- L^{-1} X on the matrix cores, skipping the zero blocks of L^{-1}.
@@ -485,60 +485,99 @@ hipError_t launch_chol_factor(const double* S, const double* Linv, int norb, dou
 }
 
 // ---------------------------------------------------------------------------
-// Y = Linv X (rows = orbitals), Linv lower triangular, n <= 256.  Workgroup:
-// 4 waves x 64 columns.  Wave w owns the 16-row tiles {w, 7-w, 8+w, 15-w}
-// (equal work: tile t needs t+1 chunks of 16 k) and all 4 column tiles.
-// Y may alias X: every wave has finished reading before any wave writes.
-// ---------------------------------------------------------------------------
-constexpr int kTrCols = 64;
+// X <- L^{-1} X for up to 256 orbitals, one 8-wave workgroup per slice of 64
+// coefficients (columns).  Chunks of 16 rows of the slice are staged in LDS
+// (double buffered, the next chunk and the next L^{-1} operands in flight
+// during the products).  Wave w owns the row tiles w and 15 - w, so every
+// wave does the same number of nonzero tile products of the triangle.  The
+// results are written after the last chunk has been read (in place is safe:
+// a workgroup only touches its own columns).
+constexpr int kTr2Cols = 64;
+constexpr int kTr2Pitch = 68;        // doubles per staged row: 2-way banks at most
 
 template <int P>
-__global__ __launch_bounds__(256) void k_trmm(const double* __restrict__ Li, const void* X, void* Y,
-                                              int64_t plane, int n, int64_t len) {
+__global__ __launch_bounds__(512) void k_trmm2(const double* __restrict__ Li, const void* X, void* Y,
+                                               int64_t plane, int n, int64_t len) {
   using T = Prec<P>;
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  __shared__ double lds[2][16 * kTr2Pitch];
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
   const int li = lane & 15, q = lane >> 4;
-  const int64_t c0 = (int64_t)blockIdx.x * kTrCols;
-  const int tiles[4] = {w, 7 - w, 8 + w, 15 - w};
+  const int64_t c0 = (int64_t)blockIdx.x * kTr2Cols;
   const int ntile = (n + 15) / 16;
-  d4 acc[4][4];
+  const int tiles[2] = {w, 15 - w};
+  // staging: thread -> (row r of the chunk, two neighbouring columns)
+  const int sr = tid >> 5, sc = (tid & 31) * 2;
+  double xs[2];
+  auto fetch = [&](int kc) {
+    const int row = 16 * kc + sr;
+    #pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int64_t col = c0 + sc + u;
+      xs[u] = (row < n && col < len) ? T::d(T::ldc(X, (int64_t)row * len + col, plane)) : 0.0;
+    }
+  };
+  auto put = [&](int buf) {
+    lds[buf][sr * kTr2Pitch + sc] = xs[0];
+    lds[buf][sr * kTr2Pitch + sc + 1] = xs[1];
+  };
+  // L^{-1} operands of chunk kc: lane (li, q) step s takes column 16 kc + 4 q + s
+  double an[2][4];
+  auto fetch_a = [&](int kc) {
+    #pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      const int row = 16 * tiles[a] + li;
+      #pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int k = 16 * kc + 4 * q + s;
+        an[a][s] = (tiles[a] >= kc && tiles[a] < ntile && row < n && k < n) ? Li[(int64_t)row * n + k]
+                                                                             : 0.0;
+      }
+    }
+  };
+  d4 acc[2][4];
   #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int a = 0; a < 2; ++a)
     #pragma unroll
     for (int c = 0; c < 4; ++c) acc[a][c] = d4{0.0, 0.0, 0.0, 0.0};
+  fetch(0);
+  fetch_a(0);
+  put(0);
+  __syncthreads();
+  int buf = 0;
   for (int kc = 0; kc < ntile; ++kc) {
-    // B chunk: rows 16 kc + 4 q + s, columns c0 + 16 c + li
-    double bv[4][4];
+    double av[2][4];
     #pragma unroll
-    for (int c = 0; c < 4; ++c)
+    for (int a = 0; a < 2; ++a)
       #pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        const int k = 16 * kc + 4 * q + s;
-        const int64_t col = c0 + 16 * c + li;
-        bv[c][s] = (k < n && col < len) ? T::d(T::ldc(X, (int64_t)k * len + col, plane)) : 0.0;
-      }
+      for (int s = 0; s < 4; ++s) av[a][s] = an[a][s];
+    const bool more = kc + 1 < ntile;
+    if (more) {
+      fetch(kc + 1);
+      fetch_a(kc + 1);
+    }
+    const double* L = lds[buf];
     #pragma unroll
-    for (int a = 0; a < 4; ++a) {
-      const int ti = tiles[a];
-      if (ti < kc || ti >= ntile) continue;
-      const int row = 16 * ti + li;
-      double av[4];
+    for (int s = 0; s < 4; ++s) {
+      double bv[4];
       #pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        const int k = 16 * kc + 4 * q + s;
-        av[s] = (row < n && k < n) ? Li[(int64_t)row * n + k] : 0.0;
-      }
+      for (int c = 0; c < 4; ++c) bv[c] = L[(4 * q + s) * kTr2Pitch + 16 * c + li];
       #pragma unroll
-      for (int s = 0; s < 4; ++s)
+      for (int a = 0; a < 2; ++a) {
+        if (tiles[a] < kc || tiles[a] >= ntile) continue;
         #pragma unroll
         for (int c = 0; c < 4; ++c)
-          acc[a][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s], bv[c][s], acc[a][c], 0, 0, 0);
+          acc[a][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a][s], bv[c], acc[a][c], 0, 0, 0);
+      }
     }
+    if (more) put(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
   }
-  __syncthreads();
+  // tile element (i, j) is in lane j + 16 (i mod 4), register i / 4
   #pragma unroll
-  for (int a = 0; a < 4; ++a) {
+  for (int a = 0; a < 2; ++a) {
     const int ti = tiles[a];
+    if (ti >= ntile) continue;
     #pragma unroll
     for (int c = 0; c < 4; ++c)
       #pragma unroll
@@ -553,11 +592,11 @@ __global__ __launch_bounds__(256) void k_trmm(const double* __restrict__ Li, con
 hipError_t launch_trmm_rows_p(int prec, const double* Li, const void* X, void* Y, int64_t plane,
                               int norb, int64_t len, hipStream_t st) {
   if (norb > 256) return hipErrorInvalidValue;
-  const int64_t nblk = (len + kTrCols - 1) / kTrCols;
+  const int64_t nblk = (len + kTr2Cols - 1) / kTr2Cols;
   switch (prec) {
-    case F64: hipLaunchKernelGGL((k_trmm<F64>), dim3((unsigned)nblk), dim3(256), 0, st, Li, X, Y, plane, norb, len); break;
-    case F32: hipLaunchKernelGGL((k_trmm<F32>), dim3((unsigned)nblk), dim3(256), 0, st, Li, X, Y, plane, norb, len); break;
-    default:  hipLaunchKernelGGL((k_trmm<F32C>), dim3((unsigned)nblk), dim3(256), 0, st, Li, X, Y, plane, norb, len); break;
+    case F64: hipLaunchKernelGGL((k_trmm2<F64>), dim3((unsigned)nblk), dim3(512), 0, st, Li, X, Y, plane, norb, len); break;
+    case F32: hipLaunchKernelGGL((k_trmm2<F32>), dim3((unsigned)nblk), dim3(512), 0, st, Li, X, Y, plane, norb, len); break;
+    default:  hipLaunchKernelGGL((k_trmm2<F32C>), dim3((unsigned)nblk), dim3(512), 0, st, Li, X, Y, plane, norb, len); break;
   }
   return hipGetLastError();
 }

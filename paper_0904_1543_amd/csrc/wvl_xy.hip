@@ -199,6 +199,7 @@ struct VecEngine {
   using T = Prec<P>;
   using V = typename T::V;
   struct Res { V r[MI][kU]; int n; };
+  static constexpr bool kGroupLoop = false;   // one launch per slot
   __device__ __forceinline__ static int pitch(int m1) { return m1 + 1; }
   template <int OP, int AX>
   __device__ __forceinline__ static void conv(V* buf, int m1, int m2, int pitch, Res& r) {
@@ -272,6 +273,7 @@ struct MfEngine {
   using T = Prec<F64>;
   using V = double;
   struct Res { d4 r[MT]; int n; };
+  static constexpr bool kGroupLoop = true;    // a group's orbitals in one workgroup
   // rows of 4 (mod 32) doubles: the x-pass operand (16 rows x 4 columns) and
   // the tile stores fall on distinct banks
   __device__ __forceinline__ static int pitch(int m1) { return m1 + ((36 - (m1 & 31)) & 31); }
@@ -457,16 +459,17 @@ __device__ __forceinline__ void xy_orbital_plane(const XyArgs& a, int b, int z, 
 
 // Grid: shared-potential batches (SHARED): blockIdx.x = z * ngroups + g; the
 // orbitals are g * G + slot, either one slot per launch (launches in slot
-// order) or, with slot < 0, all slots of the group in one workgroup, in
-// order; either way the group's density partial is accumulated in orbital
-// order.  Otherwise one (orbital, plane) per tile via the plane prefix pq.
+// order; vector engine) or all slots of the group in one workgroup, in order
+// (matrix-core engine, slot = -1); either way the group's density partial is
+// accumulated in orbital order.  Otherwise one (orbital, plane) per tile via
+// the plane prefix pq.
 template <int P, typename E, bool SHARED, int WPE>
 __global__ __launch_bounds__(kXyThreads) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
 void k_xy(XyArgs a) {
   if (SHARED) {
     const int g = blockIdx.x % a.ngroups;
     const int z = blockIdx.x / a.ngroups;
-    if (a.slot >= 0) {
+    if (!E::kGroupLoop) {
       const int b = g * a.G + a.slot;
       if (b >= a.norb) return;
       xy_orbital_plane<P, E, SHARED>(a, b, z, g, a.slot);
