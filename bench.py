@@ -56,6 +56,8 @@ def stage_model(stage, prec, variant):
     if stage == "xy_plane":
         bound = "mfma" if (prec == "f64" and variant == 2) else "alu"
         return bound, 4 * es, 2 * FLOP_AXIS + FLOP_POINTWISE
+    if stage == "z_final":       # t, c, kxy in; H*psi out
+        return "hbm", 4 * es, None
     if stage.endswith("_z") and stage.startswith(("ck", "cwt")) and variant >= 1:
         return "hbm", 3 * es, None
     if stage.startswith(("kin_", "ck_")):

@@ -82,6 +82,7 @@ struct wvl_plan {
   bool xy_ok = false;    // some form of the plane path fits (workspace reserved)
   int xy_m1 = 0, xy_m2 = 0, xy_G = 1, xy_ngroups = 0, xy_blocks = 0, xy_occ = 4;
   int xy_engine = 0;   // in-plane passes: 0 vector FMA, 1 float64 matrix cores
+  bool zfuse = true;   // last two z passes of the plane path fused (not for F32C)
   // persistent launches (WVL_PERSISTENT) of the plane path: work order by
   // decreasing cost per tile, and the number of resident workgroups
   bool persistent = false;
@@ -116,7 +117,7 @@ struct wvl_plan {
 
 // Stage ids for profiling: 1D passes are op * 3 + (axis - 1); then:
 enum { ST_POT = 15, ST_ENERGY = 16, ST_OVERLAP = 17, ST_CHOL = 18, ST_TRMM = 19, ST_XY = 29,
-       ST_RHO = 30, ST_NSTAGE = 31 };
+       ST_RHO = 30, ST_ZFIN = 31, ST_NSTAGE = 32 };
 static int stage_of(int op, int axis) {
   return op < 5 ? op * 3 + axis - 1 : 20 + (op - 5) * 3 + axis - 1;
 }
@@ -124,7 +125,7 @@ static const char* kStageNames[ST_NSTAGE] = {
     "mf_x", "mf_y", "mf_z", "mft_x", "mft_y", "mft_z", "syn_x", "syn_y", "syn_z",
     "ana_x", "ana_y", "ana_z", "kin_x", "kin_y", "kin_z", "potential", "energies",
     "overlap", "cholesky", "trmm", "cw_x", "cw_y", "cw_z", "cwt_x", "cwt_y", "cwt_z",
-    "ck_x", "ck_y", "ck_z", "xy_plane", "rho_reduce"};
+    "ck_x", "ck_y", "ck_z", "xy_plane", "rho_reduce", "z_final"};
 
 namespace {
 struct Mark {
@@ -307,6 +308,9 @@ int wvl_plan_create(wvl_ctx* ctx, const wvl_orbital* orbs, int32_t norb, int32_t
     bool ok = xy_supported(prec, p->xy_m1, p->xy_m2, mx);
     if (getenv("WVL_NO_PLANE_KERNEL")) ok = false;
     if (const char* o = getenv("WVL_PLANE_OCCUPANCY")) p->xy_occ = atoi(o) == 2 ? 2 : 4;
+    // compensated float32 keeps two windows of hi/lo pairs: fused, it drops
+    // to one wave per SIMD and is slower than the two passes
+    p->zfuse = prec != WVL_F32C && !getenv("WVL_NO_ZFUSE");
     p->use_xy = ok;
     p->xy_ok = xy_supported(prec, p->xy_m1, p->xy_m2, mx) ||
                xy_supported(prec, p->xy_m1, p->xy_m2, false);
@@ -497,6 +501,21 @@ struct Seq {
     }
     return launch_pass(p->prec, op, axis, g, n, in, out, k0, p->elems, kmul, ep, st);
   }
+  // out = W_z^T t + (kmul K_z c + kxy), one launch
+  hipError_t zfinal(const void* t, const void* c, const void* kxy, void* out, double kmul,
+                    double* ep) {
+    Mark mk(p, st, ST_ZFIN);
+    PassGeom g = gz;
+    const int n = p->pz[p->norb];
+    if (queue) {
+      g.order = p->d_order_z;
+      g.perm = p->d_perm_z;
+      g.queue = queue++;
+      g.ntiles = n;
+      g.grid = p->pgrid_pass;
+    }
+    return launch_zfinal(p->prec, g, n, t, c, kxy, out, p->elems, kmul, ep, st);
+  }
   // 3D separable operator: z pass in -> out, y pass out -> tmp, x pass tmp -> out
   hipError_t op3(int op, const void* in, void* out, void* tmp) {
     hipError_t e = pass(op, 3, in, out);
@@ -596,8 +615,12 @@ int hpsi_sequence(wvl_plan* p, hipStream_t st, const void* c, const double* V, d
       Mark mk(p, st, ST_RHO);
       WVL_CHK(launch_rho_reduce(rhop, p->xy_ngroups, p->M, V, rho, want_e ? rv : nullptr, st));
     }
-    WVL_CHK(q.pass(OP_CK, 3, c, S, S, kin_scale, want_e ? ez : nullptr));
-    WVL_CHK(q.pass(OP_CWT, 3, B, hpsi, S));
+    if (p->zfuse) {
+      WVL_CHK(q.zfinal(B, c, S, hpsi, kin_scale, want_e ? ez : nullptr));
+    } else {
+      WVL_CHK(q.pass(OP_CK, 3, c, S, S, kin_scale, want_e ? ez : nullptr));
+      WVL_CHK(q.pass(OP_CWT, 3, B, hpsi, S));
+    }
     if (want_e) {
       Mark mk(p, st, ST_ENERGY);
       // kinetic: z-pass tiles + per-plane in-plane sums; potential: per plane

@@ -27,6 +27,11 @@ __device__ __forceinline__ void block_sum_store(double v, double* dst) {
 // One 1D pass of operator `op` along `axis` (1 = contiguous, 2, 3) for every
 // orbital of the geometry.  k0 (nullable) is added to the result; epart
 // (nullable, kinetic only) receives per-tile partial sums of x * (T x).
+// out = CWT_z t + (kmul CK_z c + kxy), with the per-tile kinetic energies
+// <c, CK_z c> in epart (nullable); z lines, tiling of the z passes
+hipError_t launch_zfinal(int prec, const PassGeom& g, int ntiles, const void* t, const void* c,
+                         const void* kxy, void* out, int64_t plane, double kmul, double* epart,
+                         hipStream_t st);
 hipError_t launch_pass(int prec, int op, int axis, const PassGeom& g, int ntiles, const void* in,
                        void* out, const void* k0, int64_t plane, double kmul, double* epart,
                        hipStream_t st);

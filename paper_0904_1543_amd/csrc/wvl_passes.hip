@@ -128,6 +128,87 @@ __global__ __launch_bounds__(kThreads) void k_strided(PassGeom g, const void* __
 }
 
 // ---------------------------------------------------------------------------
+// Last step of the plane-resident H*psi, along z, fused:
+//     out = W_z^T t + (kmul K_z c + kxy)
+// (the two z passes that would otherwise write and re-read kxy), with the
+// kinetic energy <c, K_z c> of each tile.  Same association as the two
+// separate passes, so the results are the same bit for bit.
+// ---------------------------------------------------------------------------
+constexpr int kPfZ = 2;   // output pairs in flight (two register windows here)
+
+template <int P, bool EN>
+__global__ __launch_bounds__(kThreads) void k_zfinal(PassGeom g, const void* __restrict__ t,
+                                                     const void* __restrict__ c, const void* kxy,
+                                                     void* __restrict__ out, int64_t plane,
+                                                     double kmul, double* __restrict__ epart) {
+  using T = Prec<P>;
+  using V = typename T::V;
+  constexpr int LT = OpWin<OP_CWT>::OLO, HT = OpWin<OP_CWT>::OHI, WT = HT - LT + 1;
+  constexpr int LK = OpWin<OP_CK>::OLO, HK = OpWin<OP_CK>::OHI, WK = HK - LK + 1;
+  for_each_tile(g, [&](int b, int tl, int slot) {
+  const OrbDev od = g.orbs[b];
+  const int m1 = od.m[0], m2 = od.m[1], m = od.m[2];
+  const int64_t L = (int64_t)m1 * m2;
+  const int64_t line = (int64_t)tl * kThreads + threadIdx.x;
+  double e = 0.0;
+  if (line < L) {
+    const int64_t stride = L;
+    const int64_t base = od.off + line;
+    const double ks = od.kscale[2];
+    auto at = [&](int i) { return base + (int64_t)wrapi(i, m) * stride; };
+    V wt[WT + 1], wk[WK + 1];
+    #pragma unroll
+    for (int i = 0; i < WT - 1; ++i) wt[i] = T::ldc(t, at(i - HT), plane);
+    #pragma unroll
+    for (int i = 0; i < WK - 1; ++i) wk[i] = T::ldc(c, at(i - HK), plane);
+    V qt0[kPfZ], qt1[kPfZ], qk0[kPfZ], qk1[kPfZ], a0[kPfZ], a1[kPfZ];
+    auto fetch = [&](int d, int kk) {
+      qt0[d] = T::ldc(t, at(kk - LT), plane);
+      qt1[d] = T::ldc(t, at(kk + 1 - LT), plane);
+      qk0[d] = T::ldc(c, at(kk - LK), plane);
+      qk1[d] = T::ldc(c, at(kk + 1 - LK), plane);
+      a0[d] = T::ldc(kxy, base + (int64_t)kk * stride, plane);
+      a1[d] = T::ldc(kxy, base + (int64_t)(kk + 1) * stride, plane);
+    };
+    #pragma unroll
+    for (int d = 0; d < kPfZ; ++d)
+      if (2 * d < m) fetch(d, 2 * d);
+    for (int k = 0; k < m; k += 2 * kPfZ) {
+      #pragma unroll
+      for (int d = 0; d < kPfZ; ++d) {
+        const int kk = k + 2 * d;    // m is even: a pair never straddles the end
+        if (kk < m) {
+          wt[WT - 1] = qt0[d];
+          wt[WT] = qt1[d];
+          wk[WK - 1] = qk0[d];
+          wk[WK] = qk1[d];
+          const V x0 = a0[d], x1 = a1[d];
+          if (kk + 2 * kPfZ < m) fetch(d, kk + 2 * kPfZ);
+          V z0, z1, y0, y1;
+          pair_conv<P, OP_CK>(wk, z0, z1);
+          z0 = T::scale(z0, ks);
+          z1 = T::scale(z1, ks);
+          if (EN) e += T::d(wk[HK]) * T::d(z0) + T::d(wk[HK + 1]) * T::d(z1);
+          if (kmul != 1.0) { z0 = T::scale(z0, kmul); z1 = T::scale(z1, kmul); }
+          z0 = T::plus(z0, x0);
+          z1 = T::plus(z1, x1);
+          pair_conv<P, OP_CWT>(wt, y0, y1);
+          const int64_t i0 = base + (int64_t)kk * stride;
+          T::st(out, i0, plane, T::plus(y0, z0));
+          T::st(out, i0 + stride, plane, T::plus(y1, z1));
+          #pragma unroll
+          for (int i = 0; i < WT - 1; ++i) wt[i] = wt[i + 2];
+          #pragma unroll
+          for (int i = 0; i < WK - 1; ++i) wk[i] = wk[i + 2];
+        }
+      }
+    }
+  }
+  if (EN) block_sum_store(e, epart + slot);
+  });
+}
+
+// ---------------------------------------------------------------------------
 // Contiguous-axis pass (axis 1), LDS row tiles with periodic halo
 // ---------------------------------------------------------------------------
 template <int OP, int P, bool K0, bool EN>
@@ -225,6 +306,29 @@ static hipError_t launch_op(int op, int axis, const PassGeom& g, int ntiles, con
     case OP_CW:  return launch_axis<OP_CW, P>(axis, g, ntiles, in, out, k0, plane, kmul, epart, st);
     case OP_CWT: return launch_axis<OP_CWT, P>(axis, g, ntiles, in, out, k0, plane, kmul, epart, st);
     default:     return launch_axis<OP_CK, P>(axis, g, ntiles, in, out, k0, plane, kmul, epart, st);
+  }
+}
+
+template <int P>
+static hipError_t zfinal_p(const PassGeom& g, int ntiles, const void* t, const void* c,
+                           const void* kxy, void* out, int64_t plane, double kmul, double* epart,
+                           hipStream_t st) {
+  if (ntiles == 0) return hipSuccess;
+  dim3 grid(g.queue ? std::min(ntiles, g.grid) : ntiles), block(kThreads);
+  if (epart)
+    hipLaunchKernelGGL((k_zfinal<P, true>), grid, block, 0, st, g, t, c, kxy, out, plane, kmul, epart);
+  else
+    hipLaunchKernelGGL((k_zfinal<P, false>), grid, block, 0, st, g, t, c, kxy, out, plane, kmul, epart);
+  return hipGetLastError();
+}
+
+hipError_t launch_zfinal(int prec, const PassGeom& g, int ntiles, const void* t, const void* c,
+                         const void* kxy, void* out, int64_t plane, double kmul, double* epart,
+                         hipStream_t st) {
+  switch (prec) {
+    case F64: return zfinal_p<F64>(g, ntiles, t, c, kxy, out, plane, kmul, epart, st);
+    case F32: return zfinal_p<F32>(g, ntiles, t, c, kxy, out, plane, kmul, epart, st);
+    default:  return zfinal_p<F32C>(g, ntiles, t, c, kxy, out, plane, kmul, epart, st);
   }
 }
 

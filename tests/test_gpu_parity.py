@@ -271,3 +271,19 @@ def test_graph_replay_matches_eager():
         assert torch.equal(rho, ref["rho"]), rep
         assert torch.equal(en, ref["energies"]), rep
         _ = (c * 2.0).sum().item()   # unrelated eager work between replays
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_fused_last_z_pass_is_bitwise_equal(prec, monkeypatch):
+    """The fused last z step (W_z^T t + K_z c + kxy in one launch) keeps the
+    association of the two separate passes: same bits, same energies."""
+    cs = inputs.random_case(61, 3, (20, 18, 17), potential="gauss16")
+    fused = ops.Plan(cs["dims"], prec=prec)
+    monkeypatch.setenv("WVL_NO_ZFUSE", "1")
+    split = ops.Plan(cs["dims"], prec=prec)
+    c, Vt = fused.pack(cs["C"]), fused.pack_potential(cs["V"])
+    a = fused.local_hpsi(c, Vt, pot_scale=0.7, kin_scale=1.3, per_orbital=True)
+    b = split.local_hpsi(c, Vt, pot_scale=0.7, kin_scale=1.3, per_orbital=True)
+    assert torch.equal(a["hpsi"], b["hpsi"])
+    assert torch.equal(a["e_orb"], b["e_orb"])
+    assert torch.equal(a["energies"], b["energies"])
