@@ -176,7 +176,9 @@ int wvl_plan_sync(wvl_plan *plan, void *stream);
  * tiling (up to 128 x 128).  Without WVL_AUTOTUNE the environment variable
  * WVL_NO_PLANE_KERNEL forces 0 and WVL_XY_VECTOR forces 1 over 2; the
  * variable WVL_PLANE_OCCUPANCY=2 compiles the plane kernel's choice for 2
- * instead of 4 waves per SIMD.)  With WVL_AUTOTUNE, times_ms[k] (k < ntimes)
+ * instead of 4 waves per SIMD, and WVL_NO_ZFUSE runs the last z step as two
+ * passes instead of one fused launch (same results bit for bit; the fused
+ * launch is used for WVL_F64 and WVL_F32).)  With WVL_AUTOTUNE, times_ms[k] (k < ntimes)
  * receives the mean time of candidate k, or -1 where it was not available:
  * 0 one pass per axis; 1 plane kernel at 4 waves per SIMD (default engine);
  * 2 the same at 2 waves per SIMD; 3 plane kernel with the vector engine
@@ -189,7 +191,8 @@ int wvl_plan_tuning(const wvl_plan *plan, int32_t *variant, double *times_ms, in
  * launches; capacity = 0 disables.  wvl_plan_profile_read() waits for the
  * recorded events, returns up to `max` (stage id, milliseconds) pairs in
  * launch order, their number in *count, and clears the records.
- * wvl_stage_name() names a stage id ("kin_z", "potential", "overlap", ...). */
+ * wvl_stage_name() names a stage id ("kin_z", "potential", "overlap",
+ * "xy_plane", "z_final", ...). */
 int wvl_plan_profile(wvl_plan *plan, int32_t capacity);
 int wvl_plan_profile_read(wvl_plan *plan, int32_t *stage, double *ms, int32_t max,
                           int32_t *count);
