@@ -71,15 +71,20 @@ def stage_model(stage, prec, variant):
     return None, None, None
 
 
-def kernel_sources_hash():
-    """Hash of the HIP sources: a stored counter reading is only used while
-    the kernels are the ones it was taken on."""
+# the sources each profiled kernel is built from
+STAGE_SOURCES = {
+    "xy_plane": ["wvl_xy.hip", "wvl_plane.h", "wvl_kernels.h", "wvl_internal.h", "filters_gen.h"],
+}
+
+
+def kernel_sources_hash(stage):
+    """Hash of the sources of a stage's kernel: a stored counter reading is
+    only used while the kernel is the one it was taken on."""
     h = hashlib.sha256()
     cdir = os.path.join(ROOT, "paper_0904_1543_amd", "csrc")
-    for name in sorted(os.listdir(cdir)):
-        if name.endswith((".hip", ".h")):
-            with open(os.path.join(cdir, name), "rb") as f:
-                h.update(name.encode() + b"\0" + f.read())
+    for name in STAGE_SOURCES[stage]:
+        with open(os.path.join(cdir, name), "rb") as f:
+            h.update(name.encode() + b"\0" + f.read())
     return h.hexdigest()[:16]
 
 
@@ -88,12 +93,12 @@ def stored_traffic(stage):
     (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel calibration), or None
     if there is none for the current kernel sources."""
     path = os.path.join(ROOT, "profiles", f"{stage}_traffic.txt")
-    if not os.path.exists(path):
+    if stage not in STAGE_SOURCES or not os.path.exists(path):
         return None
     text = open(path).read()
     m = re.search(r"^sources_hash:\s*(\S+)", text, re.M)
     b = re.search(r"^hbm_bytes_per_launch:\s*([0-9.eE+]+)", text, re.M)
-    if not m or not b or m.group(1) != kernel_sources_hash():
+    if not m or not b or m.group(1) != kernel_sources_hash(stage):
         return None
     return float(b.group(1))
 

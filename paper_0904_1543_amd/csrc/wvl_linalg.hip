@@ -335,10 +335,20 @@ __global__ __launch_bounds__(256) void k_potrf_block(double* A, int lda, int r0,
   double* m = lds_potrf + kCb * P;
   const int t = threadIdx.x;
   const int r = t & 63, cq = t >> 6;
+  // every load is issued (outside the block: a valid element, discarded)
+  // before the first is used, so their latencies overlap
+  double v[16];
+  #pragma unroll
   for (int kk = 0; kk < 16; ++kk) {
     const int k = cq * 16 + kk;
     const bool in = r < b && k < b;
-    a[r * P + k] = in ? A[(int64_t)(r0 + r) * lda + r0 + k] : (r == k ? 1.0 : 0.0);
+    v[kk] = A[in ? (int64_t)(r0 + r) * lda + r0 + k : (int64_t)r0 * lda + r0];
+  }
+  #pragma unroll
+  for (int kk = 0; kk < 16; ++kk) {
+    const int k = cq * 16 + kk;
+    const bool in = r < b && k < b;
+    a[r * P + k] = in ? v[kk] : (r == k ? 1.0 : 0.0);
     m[r * P + k] = (r == k) ? 1.0 : 0.0;
   }
   __syncthreads();
@@ -400,6 +410,7 @@ __global__ void k_gemm_s(double* C, int ldc, const double* A, int64_t ar, int64_
   const int i = (int)(idx / N), j = (int)(idx % N);
   if (lower && j > i + diag) return;
   double s = 0.0;
+  #pragma unroll 8
   for (int k = 0; k < K; ++k) s = __builtin_fma(A[i * ar + k * ac], B[k * br + j * bc], s);
   double* c = C + (int64_t)i * ldc + j;
   *c = (beta == 0.0 ? 0.0 : beta * *c) + alpha * s;
