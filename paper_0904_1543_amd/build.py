@@ -29,8 +29,18 @@ def sources():
     return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hip"))
 
 
-def _compile(src):
+def _headers():
+    hs = [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".h")]
+    inc = os.path.join(ROOT, "include")
+    return hs + [os.path.join(inc, f) for f in os.listdir(inc) if f.endswith(".h")]
+
+
+def _compile(src, incremental=False):
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
+    if incremental and os.path.exists(obj):
+        t = os.path.getmtime(obj)
+        if all(os.path.getmtime(d) < t for d in [src] + _headers()):
+            return obj, ""
     cmd = [HIPCC] + FLAGS + ["-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
@@ -38,13 +48,21 @@ def _compile(src):
     return obj, r.stderr
 
 
-def build(verbose=False):
+def build(verbose=False, incremental=False):
+    """Compile every source (``incremental``: only those older than their
+    object file or than a header) and link libwvl.so."""
     os.makedirs(BUILD, exist_ok=True)
-    subprocess.run([sys.executable, os.path.join(CSRC, "gen_filters.py"),
-                    os.path.join(CSRC, "filters_gen.h")], check=True)
+    gen = os.path.join(CSRC, "filters_gen.h")
+    tmp_gen = gen + ".new"
+    subprocess.run([sys.executable, os.path.join(CSRC, "gen_filters.py"), tmp_gen], check=True)
+    if os.path.exists(gen) and open(gen).read() == open(tmp_gen).read():
+        os.remove(tmp_gen)      # unchanged: keep the old time stamp
+    else:
+        os.replace(tmp_gen, gen)
     srcs = sources()
-    with concurrent.futures.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
-        results = list(ex.map(_compile, srcs))
+    workers = max(1, min(16, os.cpu_count() or 1, len(srcs)))
+    with concurrent.futures.ThreadPoolExecutor(max_workers=workers) as ex:
+        results = list(ex.map(lambda s: _compile(s, incremental), srcs))
     if verbose:
         for obj, err in results:
             if err.strip():
@@ -60,4 +78,4 @@ def build(verbose=False):
 
 
 if __name__ == "__main__":
-    print(build(verbose=True))
+    print(build(verbose=True, incremental="--incremental" in sys.argv))

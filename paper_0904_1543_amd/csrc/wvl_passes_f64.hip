@@ -1,0 +1,9 @@
+// 1D pass kernels instantiated for F64.
+#include "wvl_passes_impl.h"
+
+namespace wvl {
+template hipError_t launch_op<F64>(int, int, const PassGeom&, int, const void*, void*, const void*,
+                                  int64_t, double, double*, hipStream_t);
+template hipError_t zfinal_p<F64>(const PassGeom&, int, const void*, const void*, const void*, void*,
+                                 int64_t, double, double*, hipStream_t);
+}  // namespace wvl

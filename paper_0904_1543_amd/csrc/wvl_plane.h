@@ -6,6 +6,9 @@
 namespace wvl {
 
 constexpr int kXyThreads = 512;   // threads of an in-plane workgroup (8 waves)
+constexpr int kXyWaves = kXyThreads / 64;
+constexpr int kU = 4;             // outputs per work item of the vector engine
+constexpr int kMaxItems = 8;      // vector-engine work items per thread and pass (m <= 128)
 
 // Points of the plane owned by this thread: e = threadIdx.x + k * kXyThreads,
 // with its LDS position y * pitch + x stepped incrementally.

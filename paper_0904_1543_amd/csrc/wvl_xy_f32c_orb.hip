@@ -1,0 +1,6 @@
+// In-plane kernel instantiations: F32C, vector engine, per-orbital potential.
+#include "wvl_xy_impl.h"
+
+namespace wvl {
+template void xy_launch_v<F32C, false>(const XyArgs&, int, int, size_t, hipStream_t);
+}  // namespace wvl

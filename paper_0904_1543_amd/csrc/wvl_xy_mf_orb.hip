@@ -1,0 +1,6 @@
+// In-plane kernel instantiations: float64 matrix-core engine, per-orbital potential.
+#include "wvl_xy_impl.h"
+
+namespace wvl {
+template void xy_launch_m<false>(const XyArgs&, int, int, size_t, hipStream_t);
+}  // namespace wvl
