@@ -9,12 +9,15 @@ and the Cholesky orthonormalisation of the batch (Sec. 5 step VIII).
 
 Workload: 256 orbitals on a periodic coarse grid of 48^3 (fine 96^3), the
 precision form of the method; float64 is the headline, plain float32 and
-compensated float32 (hi + lo planes) are reported beside it with their
-measured errors against the float64 oracle.  Inputs are seeded and synthetic
-and already resident in device memory when the timed region starts.  The
-uneven batch (512 orbitals, coarse dims uniform in 16..64 per axis, one
-potential per orbital, compensated float32, persistent launches replayed from
-a hipGraph, launch sequence picked by the tuner) is measured after it.
+compensated float32 (hi + lo planes) are reported beside it, each with the
+error of every result (H*psi, rho, E_loc, E_kin, per-orbital energies)
+against the float64 oracle run over the whole batch on the host cores, which
+also gives the CPU baseline.  Inputs are seeded and synthetic and already
+resident in device memory when the timed region starts.  The uneven batch
+(512 orbitals, coarse dims uniform in 16..64 per axis, one potential per
+orbital, compensated float32, persistent launches replayed from a hipGraph,
+launch sequence and tile shape picked by the tuner) is measured after it,
+with its error on sampled orbitals.
 
 Prints one JSON line.  Options: --steps K --warmup W --gpus 1.
 """
@@ -103,7 +106,7 @@ def stored_traffic(stage):
     return float(b.group(1))
 
 
-def run_precision(prec, C, V, dims, steps, warmup, sample_orbs):
+def run_precision(prec, C, V, dims, steps, warmup, keep_outputs):
     import torch
     from paper_0904_1543_amd import lib, ops
 
@@ -121,17 +124,18 @@ def run_precision(prec, C, V, dims, steps, warmup, sample_orbs):
                            ops.ptr(eorb), ops.ptr(plan.ws), ops.stream_handle())
 
     def step():
+        # local H*psi of the orbitals, then their orthonormalisation (Sec. 5,
+        # steps III and VIII)
         hpsi()
-        plan.orthonormalize(out)
+        plan.orthonormalize(c)
 
-    # accuracy of this precision on sampled orbitals (untimed)
+    # results of this precision for the accuracy check (untimed)
     hpsi()
     torch.cuda.synchronize()
-    got = {}
-    if sample_orbs:
-        allo = plan.unpack(out)
-        got = {b: allo[b].copy() for b in sample_orbs}
-        del allo
+    got = None
+    if keep_outputs:
+        got = dict(hpsi=np.stack(plan.unpack(out)), rho=rho.cpu().numpy().copy(),
+                   e_orb=eorb.cpu().numpy().copy())
     energies = en.cpu().numpy().copy()
 
     for _ in range(warmup):
@@ -171,6 +175,71 @@ def run_precision(prec, C, V, dims, steps, warmup, sample_orbs):
     return res
 
 
+def host_cpu():
+    """(threads the oracle leg uses, logical CPUs, CPU model) of this host."""
+    n = os.cpu_count() or 1
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return min(16, n), n, model
+
+
+def oracle_batch(C, V, occ, threads):
+    """The float64 oracle over every orbital of a shared-potential batch, in a
+    thread pool over orbitals (numpy releases the interpreter lock inside its
+    array operations).  Returns the reference results and the wall time of
+    the computation."""
+    from concurrent.futures import ThreadPoolExecutor
+    from oracle import wavelet as W
+
+    B = len(C)
+    hp = np.empty_like(C)
+    ekin = np.zeros(B)
+    epot = np.zeros(B)
+    parts = {}
+
+    def one(b):
+        h, psi, s = W.local_hpsi_orbital(C[b], V)
+        hp[b] = h
+        ekin[b] = float(np.sum(s * W.kinetic(s)))
+        p2 = psi * psi
+        epot[b] = float(np.sum(V * p2))
+        return b, occ[b] * p2
+
+    t = time.perf_counter()
+    with ThreadPoolExecutor(threads) as ex:
+        for b, contrib in ex.map(one, range(B)):
+            # density summed in orbital order (map returns results in order)
+            parts["rho"] = contrib if b == 0 else parts["rho"] + contrib
+    wall = time.perf_counter() - t
+    rho = parts["rho"]
+    return dict(hpsi=hp, rho=rho, e_loc=float(np.sum(V * rho)), e_kin=float(np.dot(occ, ekin)),
+                e_loc_orb=epot, e_kin_orb=ekin), wall
+
+
+def errors_vs_oracle(got, energies, ref):
+    """Per-result error of one precision: normwise ||d|| / ||ref|| and
+    elementwise max|d| / max|ref| for H*psi and rho, |d| / |ref| for E_loc and
+    E_kin and the per-orbital energies (normwise over the batch)."""
+    def pair(a, b):
+        d = a - b
+        return {"normwise": float(np.linalg.norm(d) / np.linalg.norm(b)),
+                "elementwise": float(np.max(np.abs(d)) / np.max(np.abs(b)))}
+    n = len(ref["e_kin_orb"])
+    eo = got["e_orb"]
+    return {"hpsi": pair(got["hpsi"], ref["hpsi"]),
+            "rho": pair(got["rho"], ref["rho"].ravel()),
+            "e_loc": abs(float(energies[0]) - ref["e_loc"]) / abs(ref["e_loc"]),
+            "e_kin": abs(float(energies[1]) - ref["e_kin"]) / abs(ref["e_kin"]),
+            "e_pot_orb": pair(eo[:n], ref["e_loc_orb"]),
+            "e_kin_orb": pair(eo[n:], ref["e_kin_orb"])}
+
+
 def run_uneven(steps, warmup):
     """The 512-orbital uneven batch, compensated float32, persistent launches
     in a replayed hipGraph, launch sequence chosen by the tuner."""
@@ -185,6 +254,7 @@ def run_uneven(steps, warmup):
     tune_s = time.perf_counter() - t
     c = plan.pack(wl["C"])
     Vt = plan.pack_potential(wl["V"])
+    C_host, V_host = wl["C"], wl["V"]
     del wl
     out = plan.empty()
     eorb = torch.empty(2 * plan.norb, dtype=torch.float64, device=plan.dev)
@@ -205,18 +275,44 @@ def run_uneven(steps, warmup):
     torch.cuda.synchronize()
     ms = t0.elapsed_time(t1) / steps
     v = ctypes.c_int32()
-    tm = (ctypes.c_double * 4)()
-    lib.wvl_plan_tuning(plan.h, ctypes.byref(v), tm, 4)
+    tm = (ctypes.c_double * 12)()
+    lib.wvl_plan_tuning(plan.h, ctypes.byref(v), tm, 12)
     pts = int(sum(np.prod(inputs.fine_shape(d)) for d in dims))
-    names = ["pass_by_pass", "plane_occ4", "plane_occ2", "plane_vector_engine"]
+    seqs = ["pass_by_pass", "plane_occ4", "plane_occ2", "plane_vector_engine"]
+    shapes = ["default_tiles", "half_axis1_tiles", "persistent_4_per_cu"]
+    names = [f"{a}/{b}" for a in seqs for b in shapes]
+    best = plan.query(lib.WVL_Q_TUNE_BEST)
+    # accuracy of the replayed sequence on sampled orbitals: the largest, the
+    # smallest and two others, each against the float64 oracle
+    from oracle import wavelet as W
+    got = plan.to_f64(out)
+    torch.cuda.synchronize()
+    sizes = [int(np.prod(d)) for d in dims]
+    sample = sorted({int(np.argmax(sizes)), int(np.argmin(sizes)), 0, 311})
+    num = den = 0.0
+    emax = 0.0
+    for b in sample:
+        o, m = int(plan.offsets[b]), plan.M[b]
+        g = got[o:o + m].cpu().numpy().reshape(inputs.fine_shape(dims[b]))
+        ref = W.local_hpsi_orbital(C_host[b], V_host[b])[0]
+        num += float(np.sum((g - ref) ** 2))
+        den += float(np.sum(ref ** 2))
+        emax = max(emax, float(np.max(np.abs(g - ref)) / np.max(np.abs(ref))))
     return {"workload": "512 orbitals, coarse dims uniform in 16..64 per axis (seed 5), "
                         "one 16-Gaussian potential per orbital, compensated float32, "
-                        "persistent launches replayed from a hipGraph",
+                        "replayed from a hipGraph",
             "orbital_gridpoints": pts, "ms_per_hpsi": ms,
             "orbital_gridpoints_per_s": pts / (ms * 1e-3),
-            "variant": v.value,
-            "tuner_ms": {names[i]: (tm[i] if tm[i] >= 0 else None) for i in range(4)},
-            "tuning_s": tune_s}
+            "variant": {0: "pass-by-pass", 1: "plane-resident (vector FMA)",
+                        2: "plane-resident (float64 matrix cores)"}[v.value],
+            "persistent_launches": bool(plan.query(lib.WVL_Q_PERSISTENT)),
+            "tuner_choice": names[best] if best >= 0 else None,
+            "axis1_tile_divisor": plan.query(lib.WVL_Q_XDIV),
+            "persistent_workgroups_per_cu": plan.query(lib.WVL_Q_PGRID),
+            "tuner_ms": {names[i]: tm[i] for i in range(12) if tm[i] >= 0},
+            "tuning_s": tune_s,
+            "rel_err_vs_oracle": {"orbitals": sample, "normwise": (num / den) ** 0.5,
+                                  "elementwise": emax, "tolerance": TOL["f32c"]}}
 
 
 def main():
@@ -225,8 +321,6 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--precs", default="f64,f32c,f32")
-    ap.add_argument("--cpu-orbitals", type=int, default=80,
-                    help="orbitals of the batch the oracle is timed on")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-uneven", action="store_true")
     args = ap.parse_args()
@@ -252,14 +346,14 @@ def main():
     C, V, dims = wl["C"], wl["V"], wl["dims"]
     norb = len(dims)
     pts = norb * int(np.prod(inputs.fine_shape(dims[0])))
-    sample = [] if args.no_cpu_baseline else [0, norb - 1]
 
     precs = [p for p in args.precs.split(",") if p]
     results = {}
     for prec in precs:
         print(f"[bench] {prec}: {norb} orbitals x {inputs.fine_shape(dims[0])}", file=sys.stderr,
               flush=True)
-        results[prec] = run_precision(prec, C, V, dims, args.steps, args.warmup, sample)
+        results[prec] = run_precision(prec, C, V, dims, args.steps, args.warmup,
+                                      not args.no_cpu_baseline)
         torch.cuda.empty_cache()
 
     uneven = None
@@ -269,29 +363,26 @@ def main():
         uneven = run_uneven(args.steps, args.warmup)
         torch.cuda.empty_cache()
 
-    # oracle: CPU baseline on a bounded sample, and the errors of every precision
+    # oracle over the whole batch on the host cores: the CPU baseline, and the
+    # error of every result of every precision
     cpu = None
     errors = {}
     if not args.no_cpu_baseline:
-        print(f"[bench] oracle on {args.cpu_orbitals} orbitals (one host thread)", file=sys.stderr,
+        threads, ncpu, model = host_cpu()
+        print(f"[bench] oracle on all {norb} orbitals, {threads} host threads", file=sys.stderr,
               flush=True)
-        from oracle import wavelet as W
-        ncpu = max(1, min(args.cpu_orbitals, norb))
-        idx = sorted(set([0, norb - 1] + list(range(1, ncpu - 1))))[:ncpu]
-        refs = {}
-        t = time.perf_counter()
-        for b in idx:
-            refs[b] = W.local_hpsi_orbital(C[b], V)[0]
-        tcpu = time.perf_counter() - t
-        cpu = {"value": len(idx) * pts / norb / tcpu, "unit": "orbital-gridpoints/s",
-               "cores": 1, "kind": "oracle",
-               "sample": f"local H*psi of {len(idx)} of the {norb} orbitals (fine 96^3 each), "
-                         f"plain float64 numpy oracle on one host thread, {tcpu:.1f} s; the "
-                         "overlap/Cholesky step is not in the sample"}
+        ref, tcpu = oracle_batch(C, V, wl["occ"], threads)
+        cpu = {"value": pts / tcpu, "unit": "orbital-gridpoints/s", "cores": threads,
+               "kind": "oracle",
+               "sample": f"the whole batch: local H*psi, density and energies of all {norb} "
+                         f"orbitals (fine 96^3), plain float64 numpy oracle in a pool of "
+                         f"{threads} threads over orbitals, {tcpu:.1f} s wall; host: {ncpu} "
+                         f"logical CPUs, {model}; the overlap/Cholesky step is not in the sample",
+               "host_logical_cpus": ncpu, "host_cpu_model": model}
         for prec, r in results.items():
-            num = sum(np.sum((r["got"][b] - refs[b]) ** 2) for b in r["got"])
-            den = sum(np.sum(refs[b] ** 2) for b in r["got"])
-            errors[prec] = float(np.sqrt(num / den))
+            errors[prec] = errors_vs_oracle(r["got"], r["energies"], ref)
+            r["got"] = None
+        del ref
 
     head = "f64" if "f64" in results else precs[0]
     r = results[head]
@@ -348,6 +439,10 @@ def main():
                 "hpsi_orbital_gridpoints_per_s": pts / (v["hpsi_ms"] * 1e-3),
                 "rel_err_vs_oracle": errors.get(p),
                 "tolerance": TOL[p],
+                "within_tolerance": (None if p not in errors else all(
+                    (v <= TOL[p]) if isinstance(v, float) else
+                    (v["normwise"] <= TOL[p] and v["elementwise"] <= TOL[p])
+                    for v in errors[p].values())),
                 "e_loc": float(v["energies"][0]), "e_kin": float(v["energies"][1]),
                 "stages": {k: {"avg_ms": round(s["avg_ms"], 4), "per_step": s["per_step"]}
                            for k, s in sorted(v["stages"].items(),

@@ -60,12 +60,13 @@ typedef enum { WVL_F64 = 0, WVL_F32 = 1, WVL_F32C = 2 } wvl_prec;
 /* plan flags */
 #define WVL_SHARED_V   1u  /* all orbitals share one potential (and one grid)   */
 #define WVL_USE_GRAPH  2u  /* record wvl_local_hpsi in a hipGraph and replay it  */
-/* WVL_PERSISTENT: in wvl_local_hpsi's plane-resident sequence the z passes
- * and (without WVL_SHARED_V) the in-plane kernel run as persistent launches:
- * as many workgroups as the GPU holds take tiles from a work queue, largest
- * orbitals first (longest-processing-time-first order), which balances
- * batches of uneven orbitals.  The queue counters live in the workspace, so
- * calls that share a workspace must not overlap.
+/* WVL_PERSISTENT: every pass launch of wvl_local_hpsi (z, y and x passes,
+ * the per-orbital potential stage and, without WVL_SHARED_V, the in-plane
+ * kernel) runs as a persistent launch: a fixed number of workgroups take
+ * tiles from a work queue, largest orbitals first (longest-processing-time-
+ * first order), which balances batches of uneven orbitals.  The queue
+ * counters live in the workspace, so calls that share a workspace must not
+ * overlap.
  * WVL_AUTOTUNE: at plan creation, time the launch-sequence candidates of
  * wvl_local_hpsi on the plan's own batch (temporary device buffers of about
  * three batch arrays plus the workspace) and keep the fastest; see
@@ -109,23 +110,23 @@ int wvl_plan_grid_points(const wvl_plan *plan, int64_t *points);
 
 /* Fast wavelet transform, coarse -> fine scaling coefficients (Sec. 2.1 and
  * Sec. 2.4 step 2): per axis s[(2i + j) mod m] += h_j c_i + g_j d_i.
- * `s` must not alias `c`. */
+ * `s` must not overlap `c` (WVL_EINVAL). */
 int wvl_synthesis(wvl_plan *plan, const void *c, void *s, void *ws, void *stream);
 
 /* Inverse transform (Sec. 2.4 step 6): c_i = sum_j h_j s[(2i+j) mod m],
- * d_i = sum_j g_j s[(2i+j) mod m].  `c` must not alias `s`. */
+ * d_i = sum_j g_j s[(2i+j) mod m].  `c` must not overlap `s` (WVL_EINVAL). */
 int wvl_analysis(wvl_plan *plan, const void *s, void *c, void *ws, void *stream);
 
 /* Magic filter (Sec. 2.3, Eq. "magicfilter"): out[I] = sum_l w_l in[I-l] per
  * axis; with transpose != 0 the transposed filter out[i] = sum_l w_l in[i+l]
- * (Sec. 2.4 step 3c).  `out` must not alias `in`. */
+ * (Sec. 2.4 step 3c).  `out` must not overlap `in` (WVL_EINVAL). */
 int wvl_magic_filter(wvl_plan *plan, const void *in, void *out, int transpose, void *ws,
                      void *stream);
 
 /* Kinetic operator -1/2 nabla^2 on fine scaling coefficients (Sec. 2.2,
  * Eqs. "kiner", "fprod"), with the accumulation of Sec. 3.4 (Eq. "kinetic1d"):
- * out = Kin(s) + k0.  k0 may be NULL (taken as 0) or equal to out; `out` must
- * not alias `s`. */
+ * out = Kin(s) + k0.  k0 may be NULL (taken as 0), equal to out, or disjoint
+ * from it; neither out nor k0 may overlap `s` (WVL_EINVAL). */
 int wvl_kinetic(wvl_plan *plan, const void *s, const void *k0, void *out, void *ws,
                 void *stream);
 
@@ -136,8 +137,10 @@ int wvl_local_density(wvl_plan *plan, const void *c, double *rho, int accumulate
                       void *stream);
 
 /* Local Hamiltonian (Sec. 2.4 steps 2-6): per orbital s = S c, psi = Omega s,
- * y = pot_scale V psi, Hc = A (Omega^T y + kin_scale Kin s), written to hpsi
- * (which may alias c).  Optional outputs (NULL to skip), all float64:
+ * y = pot_scale V psi, Hc = A (Omega^T y + kin_scale Kin s), written to hpsi.
+ * hpsi may be c itself (the result then replaces the coefficients); any other
+ * overlap of hpsi with c is rejected with WVL_EINVAL.  The optional outputs
+ * must not overlap c or hpsi.  Optional outputs (NULL to skip), all float64:
  *   rho    sum_b f_b psi_b^2 (WVL_SHARED_V plans; overwritten)
  *   e_loc  sum_r V rho (shared V) or sum_b f_b e_pot_b (per-orbital V)
  *   e_kin  sum_b f_b <s_b, Kin s_b>
@@ -149,6 +152,17 @@ int wvl_local_density(wvl_plan *plan, const void *c, double *rho, int accumulate
 int wvl_local_hpsi(wvl_plan *plan, const void *c, const double *V, double pot_scale,
                    double kin_scale, void *hpsi, double *rho, double *e_loc, double *e_kin,
                    double *e_orb, void *ws, void *stream);
+
+/* Gradient of the energy functional E = g_loc E_loc + g_kin E_kin with respect
+ * to the coefficients (Sec. 2 and Sec. 5: the minimisation needs the gradient
+ * of the total energy with respect to every orbital).  Both energies are
+ * quadratic forms of c_b with the symmetric operators of wvl_local_hpsi, so
+ *     grad_b = 2 f_b (g_loc Hloc + g_kin Kin) c_b
+ * with f_b the orbital's occupation; the weights are applied on the device.
+ * grad may be c itself (not a partial overlap).  Not recorded in the plan's
+ * graph (WVL_USE_GRAPH plans run it eagerly). */
+int wvl_energy_gradient(wvl_plan *plan, const void *c, const double *V, double g_loc,
+                        double g_kin, void *grad, void *ws, void *stream);
 
 /* Overlap matrix S_ij = <c_i, c_j> over all coefficients (Sec. 2.6; Sec. 5
  * step VIII), norb x norb float64, row-major.  Dense batches only. */
@@ -178,12 +192,37 @@ int wvl_plan_sync(wvl_plan *plan, void *stream);
  * variable WVL_PLANE_OCCUPANCY=2 compiles the plane kernel's choice for 2
  * instead of 4 waves per SIMD, and WVL_NO_ZFUSE runs the last z step as two
  * passes instead of one fused launch (same results bit for bit; the fused
- * launch is used for WVL_F64 and WVL_F32).)  With WVL_AUTOTUNE, times_ms[k] (k < ntimes)
- * receives the mean time of candidate k, or -1 where it was not available:
- * 0 one pass per axis; 1 plane kernel at 4 waves per SIMD (default engine);
- * 2 the same at 2 waves per SIMD; 3 plane kernel with the vector engine
- * (WVL_F64 only).  Without it times_ms is filled with -1. */
+ * launch is used for WVL_F64 and WVL_F32).)  With WVL_AUTOTUNE, times_ms[k]
+ * (k < ntimes, at most 12 candidates) receives the mean time of candidate
+ * k = 3 seq + shape, or -1 where it was not available:
+ *   seq 0 one pass per axis; 1 plane kernel at 4 waves per SIMD (default
+ *   engine); 2 the same at 2 waves per SIMD; 3 plane kernel with the vector
+ *   engine (WVL_F64 only);
+ *   shape 0 default tiles; 1 axis-1 tiles of half as many rows (seq 0 only);
+ *   2 persistent launches of 4 instead of 8 workgroups per CU (WVL_PERSISTENT
+ *   plans only).
+ * The kept candidate is reported by wvl_plan_query.  Without WVL_AUTOTUNE
+ * times_ms is filled with -1. */
 int wvl_plan_tuning(const wvl_plan *plan, int32_t *variant, double *times_ms, int32_t ntimes);
+
+/* Plan queries (*value receives the answer):
+ *   WVL_Q_VARIANT     launch sequence of wvl_local_hpsi (see wvl_plan_tuning)
+ *   WVL_Q_GROUP       orbitals per density group of the plane kernel (shared
+ *                     potential, plane sequence), 0 otherwise
+ *   WVL_Q_PERSISTENT  1 if the sequence's launches take tiles from work queues
+ *   WVL_Q_XDIV        axis-1 tiles hold 1/XDIV of the rows that fit in LDS
+ *   WVL_Q_PGRID       workgroups per CU of the persistent pass launches
+ *   WVL_Q_TUNE_BEST   tuner candidate kept (index into times_ms), -1 untuned
+ *   WVL_Q_FUSED_Z     1 if the last z step runs as one fused launch (it does
+ *                     not when hpsi is c; see wvl_local_hpsi) */
+#define WVL_Q_VARIANT 0
+#define WVL_Q_GROUP 1
+#define WVL_Q_PERSISTENT 2
+#define WVL_Q_XDIV 3
+#define WVL_Q_PGRID 4
+#define WVL_Q_TUNE_BEST 5
+#define WVL_Q_FUSED_Z 6
+int wvl_plan_query(const wvl_plan *plan, int32_t what, int64_t *value);
 
 /* Launch profiling: with capacity > 0, every kernel launch of the following
  * calls on this plan (eager mode; graph replays are not split) is bracketed

@@ -11,30 +11,16 @@ so
     dE_loc/dc_i = 2 f_i Hloc c_i,   dE_kin/dc_i = 2 f_i Kin c_i,
     dE_loc/dV   = rho = sum_i f_i psi_i^2.
 The backward pass is therefore one more local H*psi with its two parts
-weighted by the incoming gradients (pot_scale = g_loc, kin_scale = g_kin), run
-by the library like the forward one; torch only holds the buffers.
+weighted by the incoming gradients and the occupations (wvl_energy_gradient),
+run by the library like the forward one; torch only holds the buffers.
 
 Inputs are float64 tensors; a plan of another precision converts them on the
 device (the compensated form keeps about 1e-10 of relative accuracy).
 """
 
-import numpy as np
 import torch
 
 from . import ops
-
-
-def _occupation_vector(plan):
-    """Per-element occupation f_i (cached on the plan), or None if uniform."""
-    occ = np.asarray(plan.occ, dtype=np.float64)
-    if np.all(occ == occ[0]):
-        return None
-    v = getattr(plan, "_occ_elems", None)
-    if v is None:
-        reps = torch.as_tensor(np.asarray(plan.M, dtype=np.int64))
-        v = torch.repeat_interleave(torch.as_tensor(occ), reps).to(plan.dev)
-        plan._occ_elems = v
-    return v
 
 
 def _to_plan(plan, c64):
@@ -68,14 +54,8 @@ class LocalEnergy(torch.autograd.Function):
         gk = 0.0 if g_kin is None else float(g_kin)
         grad_c = grad_V = None
         if ctx.needs_input_grad[0]:
-            occ = _occupation_vector(plan)
-            # uniform occupation: 2 f goes into the two weights
-            s = 2.0 * float(plan.occ[0]) if occ is None else 2.0
-            r = plan.local_hpsi(_to_plan(plan, c), V, pot_scale=s * gl, kin_scale=s * gk,
-                                rho=False, energies=False)
-            grad_c = plan.to_f64(r["hpsi"])
-            if occ is not None:
-                grad_c = grad_c * occ
+            # 2 f_b (g_loc Hloc + g_kin Kin) c_b, occupations applied by the library
+            grad_c = plan.to_f64(plan.energy_gradient(_to_plan(plan, c), V, gl, gk))
         if ctx.needs_input_grad[1]:
             if not plan.shared_v:
                 raise NotImplementedError("dE/dV needs a shared potential")

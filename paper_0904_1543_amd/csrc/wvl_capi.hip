@@ -71,6 +71,7 @@ struct wvl_plan {
   int norb = 0;
   bool shared = false;   // shared potential + uniform grid
   bool dense = false;    // off_b = b * M, all dims equal
+  bool occ_uniform = true;  // every orbital has the same occupation
   int64_t M = 0;         // points per orbital when uniform
   int64_t elems = 0;     // elements per packed plane
   int64_t vlen = 0;      // minimal length of a per-orbital V buffer
@@ -86,8 +87,12 @@ struct wvl_plan {
   // persistent launches (WVL_PERSISTENT) of the plane path: work order by
   // decreasing cost per tile, and the number of resident workgroups
   bool persistent = false;
-  std::vector<int32_t> perm_z, order_z, perm_q, order_q;
+  std::vector<int32_t> perm_z, order_z, perm_q, order_q, px2, perm_y, order_y, perm_x, order_x,
+      order_x2, perm_p, order_p;
   int pgrid_pass = 0;
+  // launch shape (picked by the tuner): axis-1 rows-per-tile divisor and
+  // workgroups per CU of the persistent pass launches
+  int xdiv = 1, pgrid_mul = 8;
   // device copies
   OrbDev* d_orbs = nullptr;
   int32_t* d_pz = nullptr;
@@ -96,6 +101,8 @@ struct wvl_plan {
   int32_t* d_pp = nullptr;
   int32_t* d_pq = nullptr;
   int32_t *d_perm_z = nullptr, *d_order_z = nullptr, *d_perm_q = nullptr, *d_order_q = nullptr;
+  int32_t *d_px2 = nullptr, *d_perm_y = nullptr, *d_order_y = nullptr, *d_perm_x = nullptr,
+          *d_order_x = nullptr, *d_order_x2 = nullptr, *d_perm_p = nullptr, *d_order_p = nullptr;
   int* d_info = nullptr;
   // workspace layout (byte offsets)
   size_t ws = 0, o_A = 0, o_B = 0, o_S = 0, o_ez = 0, o_ey = 0, o_ex = 0, o_pp = 0, o_rv = 0,
@@ -107,6 +114,7 @@ struct wvl_plan {
   hipGraphExec_t gexec = nullptr;
   GraphKey gkey{};
   int variant = 0;
+  int tune_best = -1;            // tuner: index of the candidate kept
   std::vector<double> tune_ms;
   // launch profiling (hipEvent pairs around every launch of a call)
   struct Rec { int stage; hipEvent_t a, b; };
@@ -151,6 +159,9 @@ struct Mark {
 
 static int esize(int prec) { return prec == WVL_F32 ? 4 : 8; }
 
+constexpr int kQueueCounters = 16;   // work-queue counters per launch sequence
+constexpr int kTuneCands = 12;       // launch candidates of the tuner (4 sequences x 3 shapes)
+
 static int check_plan(const wvl_plan* p) {
   if (!p) return fail(WVL_EINVAL, "plan is NULL");
   return WVL_OK;
@@ -164,6 +175,23 @@ static int check_gpu(const wvl_plan* p) {
 }
 
 static inline char* wsp(void* ws, size_t off) { return (char*)ws + off; }
+
+// bytes of one packed batch array of the plan (both planes for WVL_F32C)
+static size_t batch_bytes(const wvl_plan* p) {
+  return (size_t)p->elems * (p->prec == WVL_F32 ? 4 : 8);
+}
+
+static bool overlap(const void* a, size_t na, const void* b, size_t nb) {
+  const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
+  return x < y + nb && y < x + na;
+}
+
+// input and output batch arrays of an operation must not share memory
+static int check_disjoint(const wvl_plan* p, const void* in, const void* out, const char* what) {
+  if (overlap(in, batch_bytes(p), out, batch_bytes(p)))
+    return fail(WVL_EINVAL, "%s: output overlaps input", what);
+  return WVL_OK;
+}
 
 namespace {
 int autotune(wvl_plan* p);
@@ -276,6 +304,8 @@ int wvl_plan_create(wvl_ctx* ctx, const wvl_orbital* orbs, int32_t norb, int32_t
   }
   p->shared = (flags & WVL_SHARED_V) != 0;
   p->dense = dense && uniform;
+  for (int b = 1; b < norb; ++b)
+    if (p->orbs[b].occ != p->orbs[0].occ) p->occ_uniform = false;
   p->M = uniform ? (int64_t)p->orbs[0].m[0] * p->orbs[0].m[1] * p->orbs[0].m[2] : 0;
   p->elems = end;
   if (end > ((int64_t)1 << 40)) { delete p; return fail(WVL_EINVAL, "batch too large"); }
@@ -285,16 +315,21 @@ int wvl_plan_create(wvl_ctx* ctx, const wvl_orbital* orbs, int32_t norb, int32_t
   p->px.assign(norb + 1, 0);
   p->pp.assign(norb + 1, 0);
   p->pq.assign(norb + 1, 0);
+  p->px2.assign(norb + 1, 0);
   for (int b = 0; b < norb; ++b) {
     const OrbDev& d = p->orbs[b];
     const int64_t m1 = d.m[0], m2 = d.m[1], m3 = d.m[2];
-    const int64_t R = std::max<int64_t>(1, kContigLds / (m1 + 2 * kHalo));
+    const int64_t R = contig_rows((int)m1, 1), R2 = contig_rows((int)m1, 2);
     p->pz[b + 1] = p->pz[b] + (int32_t)((m1 * m2 + kThreads - 1) / kThreads);
     p->py[b + 1] = p->py[b] + (int32_t)((m1 * m3 + kThreads - 1) / kThreads);
     p->px[b + 1] = p->px[b] + (int32_t)((m2 * m3 + R - 1) / R);
+    p->px2[b + 1] = p->px2[b] + (int32_t)((m2 * m3 + R2 - 1) / R2);
     p->pp[b + 1] = p->pp[b] + (int32_t)((m1 * m2 * m3 + kThreads - 1) / kThreads);
     p->pq[b + 1] = p->pq[b] + (int32_t)m3;
-    if (p->pp[b + 1] < 0 || p->pz[b + 1] < 0) { delete p; return fail(WVL_EINVAL, "too many tiles"); }
+    if (p->pp[b + 1] < 0 || p->pz[b + 1] < 0 || p->px2[b + 1] < 0) {
+      delete p;
+      return fail(WVL_EINVAL, "too many tiles");
+    }
   }
   p->nblk = p->shared ? (int)((p->M + kThreads - 1) / kThreads) : 0;
   // plane-resident path: every orbital's (m1, m2) plane must fit the kernel
@@ -342,8 +377,23 @@ int wvl_plan_create(wvl_ctx* ctx, const wvl_orbital* orbs, int32_t norb, int32_t
     build(p->perm_z, p->order_z, p->pz, [&](int b) { return (int64_t)p->orbs[b].m[2]; });
     build(p->perm_q, p->order_q, p->pq,
           [&](int b) { return (int64_t)p->orbs[b].m[0] * p->orbs[b].m[1]; });
+    // pass-by-pass sequence: y tiles cost ~ m2, x tiles ~ their rows x m1,
+    // pointwise tiles are all alike
+    build(p->perm_y, p->order_y, p->py, [&](int b) { return (int64_t)p->orbs[b].m[1]; });
+    build(p->perm_x, p->order_x, p->px, [&](int b) {
+      const int m1 = p->orbs[b].m[0];
+      return (int64_t)contig_rows(m1, 1) * m1;
+    });
+    {
+      std::vector<int32_t> tmp;
+      build(tmp, p->order_x2, p->px2, [&](int b) {
+        const int m1 = p->orbs[b].m[0];
+        return (int64_t)contig_rows(m1, 1) * m1;
+      });
+    }
+    build(p->perm_p, p->order_p, p->pp, [&](int) { return (int64_t)0; });
     p->persistent = (flags & WVL_PERSISTENT) != 0;
-    p->pgrid_pass = std::max(1, ctx->cus) * 8;
+    p->pgrid_pass = std::max(1, ctx->cus) * p->pgrid_mul;
   }
   // workspace layout
   size_t off = 0;
@@ -353,7 +403,7 @@ int wvl_plan_create(wvl_ctx* ctx, const wvl_orbital* orbs, int32_t norb, int32_t
   p->o_S = off; off += arr;
   p->o_ez = off; off += align256(sizeof(double) * p->pz[norb]);
   p->o_ey = off; off += align256(sizeof(double) * p->py[norb]);
-  p->o_ex = off; off += align256(sizeof(double) * p->px[norb]);
+  p->o_ex = off; off += align256(sizeof(double) * std::max(p->px[norb], p->px2[norb]));
   p->o_pp = off;
   off += align256(sizeof(double) * (p->shared ? (size_t)norb * p->nblk : (size_t)p->pp[norb]));
   p->o_rv = off; off += align256(sizeof(double) * (size_t)std::max(p->nblk, 1));
@@ -373,12 +423,12 @@ int wvl_plan_create(wvl_ctx* ctx, const wvl_orbital* orbs, int32_t norb, int32_t
     p->o_epl = off; off += align256(sizeof(double) * (size_t)p->pq[norb]);
     p->o_kpl = off; off += align256(sizeof(double) * (size_t)p->pq[norb]);
   }
-  p->o_queue = off; off += 256;   // work-queue counters of persistent launches
+  p->o_queue = off; off += align256(sizeof(int32_t) * kQueueCounters);   // work-queue counters
   p->ws = off;
   if (!ctx->dry) {
     hipError_t e = hipSetDevice(ctx->device);
     if (e == hipSuccess) e = hipMalloc((void**)&p->d_orbs, sizeof(OrbDev) * norb);
-    if (e == hipSuccess) e = hipMalloc((void**)&p->d_pz, sizeof(int32_t) * (norb + 1) * 9);
+    if (e == hipSuccess) e = hipMalloc((void**)&p->d_pz, sizeof(int32_t) * (norb + 1) * 17);
     if (e == hipSuccess) e = hipMalloc((void**)&p->d_info, sizeof(int) * 4);
     if (e != hipSuccess) {
       wvl_plan_destroy(p);
@@ -392,13 +442,22 @@ int wvl_plan_create(wvl_ctx* ctx, const wvl_orbital* orbs, int32_t norb, int32_t
     p->d_order_z = p->d_perm_z + (norb + 1);
     p->d_perm_q = p->d_order_z + (norb + 1);
     p->d_order_q = p->d_perm_q + (norb + 1);
+    p->d_px2 = p->d_order_q + (norb + 1);
+    p->d_perm_y = p->d_px2 + (norb + 1);
+    p->d_order_y = p->d_perm_y + (norb + 1);
+    p->d_perm_x = p->d_order_y + (norb + 1);
+    p->d_order_x = p->d_perm_x + (norb + 1);
+    p->d_order_x2 = p->d_order_x + (norb + 1);
+    p->d_perm_p = p->d_order_x2 + (norb + 1);
+    p->d_order_p = p->d_perm_p + (norb + 1);
     std::vector<int32_t> all;
     all.insert(all.end(), p->pz.begin(), p->pz.end());
     all.insert(all.end(), p->py.begin(), p->py.end());
     all.insert(all.end(), p->px.begin(), p->px.end());
     all.insert(all.end(), p->pp.begin(), p->pp.end());
     all.insert(all.end(), p->pq.begin(), p->pq.end());
-    for (auto* v : {&p->perm_z, &p->order_z, &p->perm_q, &p->order_q}) {
+    for (auto* v : {&p->perm_z, &p->order_z, &p->perm_q, &p->order_q, &p->px2, &p->perm_y,
+                    &p->order_y, &p->perm_x, &p->order_x, &p->order_x2, &p->perm_p, &p->order_p}) {
       all.insert(all.end(), v->begin(), v->end());
       all.resize(all.size() + (norb + 1 - v->size()), 0);
     }
@@ -480,26 +539,46 @@ struct Seq {
   wvl_plan* p;
   hipStream_t st;
   PassGeom gz, gy, gx, gp;
-  int32_t* queue = nullptr;   // persistent z passes: next free counter
+  int32_t* queue = nullptr;   // persistent launches: next free work-queue counter
+  int32_t* queue_end = nullptr;
   Seq(wvl_plan* pl, hipStream_t s) : p(pl), st(s) {
     gz = PassGeom{p->d_orbs, p->d_pz, p->norb};
     gy = PassGeom{p->d_orbs, p->d_py, p->norb};
-    gx = PassGeom{p->d_orbs, p->d_px, p->norb};
+    gx = PassGeom{p->d_orbs, p->xdiv == 2 ? p->d_px2 : p->d_px, p->norb};
+    gx.xdiv = p->xdiv;
     gp = PassGeom{p->d_orbs, p->d_pp, p->norb};
+  }
+  int ntiles(int axis) const {
+    return axis == 1 ? (p->xdiv == 2 ? p->px2[p->norb] : p->px[p->norb])
+         : axis == 2 ? p->py[p->norb] : p->pz[p->norb];
+  }
+  // persistent form of a launch over `n` tiles: work order and a fresh counter
+  bool make_persistent(PassGeom& g, int n, const int32_t* order, const int32_t* perm) {
+    if (!queue || queue >= queue_end) return false;
+    g.order = order;
+    g.perm = perm;
+    g.queue = queue++;
+    g.ntiles = n;
+    g.grid = p->pgrid_pass;
+    return true;
   }
   hipError_t pass(int op, int axis, const void* in, void* out, const void* k0 = nullptr,
                   double kmul = 1.0, double* ep = nullptr) {
     Mark mk(p, st, stage_of(op, axis));
     PassGeom g = axis == 1 ? gx : axis == 2 ? gy : gz;
-    const int n = axis == 1 ? p->px[p->norb] : axis == 2 ? p->py[p->norb] : p->pz[p->norb];
-    if (axis == 3 && queue) {
-      g.order = p->d_order_z;
-      g.perm = p->d_perm_z;
-      g.queue = queue++;
-      g.ntiles = n;
-      g.grid = p->pgrid_pass;
+    const int n = ntiles(axis);
+    if (queue) {
+      if (axis == 3) make_persistent(g, n, p->d_order_z, p->d_perm_z);
+      else if (axis == 2) make_persistent(g, n, p->d_order_y, p->d_perm_y);
+      else make_persistent(g, n, p->xdiv == 2 ? p->d_order_x2 : p->d_order_x, p->d_perm_x);
     }
     return launch_pass(p->prec, op, axis, g, n, in, out, k0, p->elems, kmul, ep, st);
+  }
+  hipError_t pot_orb(const void* psi, void* y, const double* V, double pot_scale, double* pp) {
+    PassGeom g = gp;
+    const int n = p->pp[p->norb];
+    if (queue) make_persistent(g, n, p->d_order_p, p->d_perm_p);
+    return launch_pot_orb(p->prec, g, n, psi, y, V, pot_scale, p->elems, pp, st);
   }
   // out = W_z^T t + (kmul K_z c + kxy), one launch
   hipError_t zfinal(const void* t, const void* c, const void* kxy, void* out, double kmul,
@@ -507,13 +586,7 @@ struct Seq {
     Mark mk(p, st, ST_ZFIN);
     PassGeom g = gz;
     const int n = p->pz[p->norb];
-    if (queue) {
-      g.order = p->d_order_z;
-      g.perm = p->d_perm_z;
-      g.queue = queue++;
-      g.ntiles = n;
-      g.grid = p->pgrid_pass;
-    }
+    if (queue) make_persistent(g, n, p->d_order_z, p->d_perm_z);
     return launch_zfinal(p->prec, g, n, t, c, kxy, out, p->elems, kmul, ep, st);
   }
   // 3D separable operator: z pass in -> out, y pass out -> tmp, x pass tmp -> out
@@ -531,6 +604,10 @@ struct Seq {
     if (_e != hipSuccess) return hipfail(_e, "kernel launch"); \
   } while (0)
 
+// The local H*psi launch sequence (Sec. 2.4 steps 2-6 with the density of
+// Sec. 2.5 and the float64 energies).  hpsi may be c itself: then the last z
+// step runs as two passes (the fused one would overwrite c at the start of a
+// z line before its periodic wrap reads it back).
 int hpsi_sequence(wvl_plan* p, hipStream_t st, const void* c, const double* V, double pot_scale,
                   double kin_scale, void* hpsi, double* rho, double* e_loc, double* e_kin,
                   double* e_orb, void* ws) {
@@ -545,18 +622,18 @@ int hpsi_sequence(wvl_plan* p, hipStream_t st, const void* c, const double* V, d
   double* rv = (double*)wsp(ws, p->o_rv);
   double* eorb = e_orb ? e_orb : (double*)wsp(ws, p->o_eorb);
   const bool want_e = e_loc || e_kin || e_orb;
+  if (p->persistent) {
+    int32_t* queue = (int32_t*)wsp(ws, p->o_queue);
+    WVL_CHK(launch_fill_int(queue, kQueueCounters, st));
+    q.queue = queue;
+    q.queue_end = queue + kQueueCounters;
+  }
   if (p->use_xy) {
     // z pass: u = W_z c; planes: psi, rho, y, t = W_y^T W_x^T y, kxy;
     // z passes: kxy += K_z c, then Hc = W_z^T t + kxy
     double* epl = (double*)wsp(ws, p->o_epl);
     double* kpl = (double*)wsp(ws, p->o_kpl);
     double* rhop = p->shared ? (double*)wsp(ws, p->o_rhop) : nullptr;
-    int32_t* queue = (int32_t*)wsp(ws, p->o_queue);
-    if (p->persistent) {
-      // counters: z passes 0..2, in-plane kernel 3
-      WVL_CHK(launch_fill_int(queue, 4, st));
-      q.queue = queue;
-    }
     WVL_CHK(q.pass(OP_CW, 3, c, A));
     {
       XyArgs xa;
@@ -585,10 +662,10 @@ int hpsi_sequence(wvl_plan* p, hipStream_t st, const void* c, const double* V, d
       xa.queue = nullptr;
       xa.ntiles = p->xy_blocks;
       int nblocks = p->xy_blocks;
-      if (p->persistent && !p->shared) {
+      if (q.queue && !p->shared && q.queue < q.queue_end) {
         xa.order = p->d_order_q;
         xa.perm = p->d_perm_q;
-        xa.queue = queue + 3;
+        xa.queue = q.queue++;
         const size_t lds = xy_lds_bytes(p->prec, p->xy_m1, p->xy_m2, p->xy_engine != 0);
         const int per_cu = std::max(1, std::min(p->xy_occ / 2, (int)(p->ctx->lds_per_block / lds)));
         nblocks = std::min(nblocks, std::max(1, p->ctx->cus) * per_cu);
@@ -615,7 +692,7 @@ int hpsi_sequence(wvl_plan* p, hipStream_t st, const void* c, const double* V, d
       Mark mk(p, st, ST_RHO);
       WVL_CHK(launch_rho_reduce(rhop, p->xy_ngroups, p->M, V, rho, want_e ? rv : nullptr, st));
     }
-    if (p->zfuse) {
+    if (p->zfuse && hpsi != c) {
       WVL_CHK(q.zfinal(B, c, S, hpsi, kin_scale, want_e ? ez : nullptr));
     } else {
       WVL_CHK(q.pass(OP_CK, 3, c, S, S, kin_scale, want_e ? ez : nullptr));
@@ -643,8 +720,7 @@ int hpsi_sequence(wvl_plan* p, hipStream_t st, const void* c, const double* V, d
       WVL_CHK(launch_pot_shared(p->prec, p->d_orbs, p->norb, p->M, B, B, V, pot_scale, p->elems,
                                 rho, 0, want_e ? rv : nullptr, e_orb ? pp : nullptr, st));
     } else {
-      WVL_CHK(launch_pot_orb(p->prec, q.gp, p->pp[p->norb], B, B, V, pot_scale, p->elems,
-                             want_e ? pp : nullptr, st));
+      WVL_CHK(q.pot_orb(B, B, V, pot_scale, want_e ? pp : nullptr));
     }
   }
   // steps 3c + 6 combined (transposed magic filter then analysis): W3^T y
@@ -660,7 +736,8 @@ int hpsi_sequence(wvl_plan* p, hipStream_t st, const void* c, const double* V, d
   if (want_e) {
     Mark mk(p, st, ST_ENERGY);
     const int pot_mode = p->shared ? (e_orb ? 2 : 0) : 1;
-    WVL_CHK(launch_orb_sums(p->d_orbs, p->norb, p->d_pz, p->d_py, p->d_px, ez, ey, ex, pp, pot_mode,
+    WVL_CHK(launch_orb_sums(p->d_orbs, p->norb, p->d_pz, p->d_py,
+                            p->xdiv == 2 ? p->d_px2 : p->d_px, ez, ey, ex, pp, pot_mode,
                             p->d_pp, p->nblk, eorb, st));
     if (e_loc || e_kin)
       WVL_CHK(launch_totals(p->d_orbs, p->norb, eorb, rv, p->shared ? p->nblk : 0, e_loc, e_kin, st));
@@ -668,23 +745,40 @@ int hpsi_sequence(wvl_plan* p, hipStream_t st, const void* c, const double* V, d
   return WVL_OK;
 }
 
-// Candidates of the hpsi launch sequence, timed on the plan's own batch (zero
-// data: no kernel's work depends on values), in this order:
-//   0: one 1D pass per axis and operator;
-//   1: plane-resident kernel, 4 waves per SIMD, default engine;
-//   2: plane-resident kernel, 2 waves per SIMD, default engine;
-//   3: plane-resident kernel, 4 waves per SIMD, vector FMA engine (float64
-//      only, where the matrix-core engine is the default).
+// Launch candidates of wvl_local_hpsi, timed on the plan's own batch (zero
+// data: no kernel's work depends on values).  Candidate k = 3 * seq + shape:
+//   seq 0: one 1D pass per axis and operator;
+//   seq 1: plane-resident kernel, 4 waves per SIMD, default engine;
+//   seq 2: plane-resident kernel, 2 waves per SIMD, default engine;
+//   seq 3: plane-resident kernel, 4 waves per SIMD, vector FMA engine
+//          (float64 only, where the matrix-core engine is the default);
+//   shape 0: default tiles (axis-1 tiles as many rows as fit in LDS;
+//            persistent launches of 8 workgroups per CU);
+//   shape 1: axis-1 tiles of half as many rows (seq 0 only: the other
+//            sequences have no axis-1 pass);
+//   shape 2: persistent launches of 4 workgroups per CU (persistent plans).
 // Unavailable candidates get -1.  The fastest one is kept.
+struct Cand { bool xy; int occ, engine, xdiv, pmul; };
+
+void apply_cand(wvl_plan* p, const Cand& c) {
+  p->use_xy = c.xy;
+  p->xy_occ = c.occ;
+  p->xy_engine = c.engine;
+  p->xdiv = c.xdiv;
+  p->pgrid_mul = c.pmul;
+  p->pgrid_pass = std::max(1, p->ctx->cus) * c.pmul;
+  p->variant = c.xy ? 1 + c.engine : 0;
+}
+
 int autotune(wvl_plan* p) {
-  struct Cand { bool xy; int occ, engine; };
   const bool mx = xy_matrix_engine(p->prec, p->xy_m1, p->xy_m2);
-  const bool plane_ok = xy_supported(p->prec, p->xy_m1, p->xy_m2, mx);
-  const bool vec_ok = xy_supported(p->prec, p->xy_m1, p->xy_m2, false);
-  const Cand cands[4] = {{false, 4, 0}, {true, 4, mx ? 1 : 0}, {true, 2, mx ? 1 : 0}, {true, 4, 0}};
-  const bool avail[4] = {true, plane_ok, plane_ok, mx && vec_ok};
+  const bool plane_ok = xy_supported(p->prec, p->xy_m1, p->xy_m2, mx) && !getenv("WVL_NO_PLANE_KERNEL");
+  const bool vec_ok = xy_supported(p->prec, p->xy_m1, p->xy_m2, false) && !getenv("WVL_NO_PLANE_KERNEL");
+  const Cand seqs[4] = {{false, 4, 0, 1, 8}, {true, 4, mx ? 1 : 0, 1, 8}, {true, 2, mx ? 1 : 0, 1, 8},
+                        {true, 4, 0, 1, 8}};
+  const bool seq_ok[4] = {true, plane_ok, plane_ok, mx && vec_ok};
   const size_t es = p->prec == WVL_F32 ? 4 : 8;
-  const size_t arr = (size_t)p->elems * es;
+  const size_t arr = (size_t)p->elems * (p->prec == WVL_F32C ? 8 : es);
   const size_t vbytes = sizeof(double) * (size_t)(p->shared ? p->M : std::max<int64_t>(p->vlen, 1));
   void *c = nullptr, *out = nullptr, *ws = nullptr, *V = nullptr, *e = nullptr;
   hipStream_t st = nullptr;
@@ -701,15 +795,19 @@ int autotune(wvl_plan* p) {
   if (err == hipSuccess) err = hipMemsetAsync(V, 0, vbytes, st);
   int status = WVL_OK;
   if (err != hipSuccess) status = hipfail(err, "autotune buffers");
-  const Cand keep{p->use_xy, p->xy_occ, p->xy_engine};
+  const Cand keep{p->use_xy, p->xy_occ, p->xy_engine, p->xdiv, p->pgrid_mul};
   int best = -1;
   double best_ms = 0.0;
-  p->tune_ms.assign(4, -1.0);
-  for (int k = 0; k < 4 && status == WVL_OK; ++k) {
-    if (!avail[k]) continue;
-    p->use_xy = cands[k].xy;
-    p->xy_occ = cands[k].occ;
-    p->xy_engine = cands[k].engine;
+  p->tune_ms.assign(kTuneCands, -1.0);
+  for (int k = 0; k < kTuneCands && status == WVL_OK; ++k) {
+    const int seq = k / 3, shape = k % 3;
+    if (!seq_ok[seq]) continue;
+    if (shape == 1 && seq != 0) continue;
+    if (shape == 2 && !p->persistent) continue;
+    Cand cd = seqs[seq];
+    if (shape == 1) cd.xdiv = 2;
+    if (shape == 2) cd.pmul = 4;
+    apply_cand(p, cd);
     double* ed = (double*)e;
     status = hpsi_sequence(p, st, c, (const double*)V, 1.0, 1.0, out, nullptr, ed, ed + 1,
                            nullptr, ws);   // warm-up
@@ -729,15 +827,14 @@ int autotune(wvl_plan* p) {
     if (best < 0 || p->tune_ms[k] < best_ms) { best = k; best_ms = p->tune_ms[k]; }
   }
   if (best >= 0 && status == WVL_OK) {
-    p->use_xy = cands[best].xy;
-    p->xy_occ = cands[best].occ;
-    p->xy_engine = cands[best].engine;
+    Cand cd = seqs[best / 3];
+    if (best % 3 == 1) cd.xdiv = 2;
+    if (best % 3 == 2) cd.pmul = 4;
+    apply_cand(p, cd);
+    p->tune_best = best;
   } else {
-    p->use_xy = keep.xy;
-    p->xy_occ = keep.occ;
-    p->xy_engine = keep.engine;
+    apply_cand(p, keep);
   }
-  p->variant = p->use_xy ? 1 + p->xy_engine : 0;
   if (st) (void)hipStreamSynchronize(st);
   if (t0) (void)hipEventDestroy(t0);
   if (t1) (void)hipEventDestroy(t1);
@@ -754,7 +851,7 @@ extern "C" {
 int wvl_synthesis(wvl_plan* p, const void* c, void* s, void* ws, void* stream) {
   if (int r = check_plan(p)) return r;
   if (!c || !s || !ws) return fail(WVL_EINVAL, "wvl_synthesis: NULL pointer");
-  if (c == s) return fail(WVL_EINVAL, "wvl_synthesis: output aliases input");
+  if (int r = check_disjoint(p, c, s, "wvl_synthesis")) return r;
   if (int r = check_gpu(p)) return r;
   Seq q(p, (hipStream_t)stream);
   WVL_CHK(q.op3(OP_SYN, c, s, wsp(ws, p->o_A)));
@@ -764,7 +861,7 @@ int wvl_synthesis(wvl_plan* p, const void* c, void* s, void* ws, void* stream) {
 int wvl_analysis(wvl_plan* p, const void* s, void* c, void* ws, void* stream) {
   if (int r = check_plan(p)) return r;
   if (!c || !s || !ws) return fail(WVL_EINVAL, "wvl_analysis: NULL pointer");
-  if (c == s) return fail(WVL_EINVAL, "wvl_analysis: output aliases input");
+  if (int r = check_disjoint(p, s, c, "wvl_analysis")) return r;
   if (int r = check_gpu(p)) return r;
   Seq q(p, (hipStream_t)stream);
   WVL_CHK(q.op3(OP_ANA, s, c, wsp(ws, p->o_A)));
@@ -775,7 +872,7 @@ int wvl_magic_filter(wvl_plan* p, const void* in, void* out, int transpose, void
                      void* stream) {
   if (int r = check_plan(p)) return r;
   if (!in || !out || !ws) return fail(WVL_EINVAL, "wvl_magic_filter: NULL pointer");
-  if (in == out) return fail(WVL_EINVAL, "wvl_magic_filter: output aliases input");
+  if (int r = check_disjoint(p, in, out, "wvl_magic_filter")) return r;
   if (int r = check_gpu(p)) return r;
   Seq q(p, (hipStream_t)stream);
   WVL_CHK(q.op3(transpose ? OP_MFT : OP_MF, in, out, wsp(ws, p->o_A)));
@@ -785,8 +882,11 @@ int wvl_magic_filter(wvl_plan* p, const void* in, void* out, int transpose, void
 int wvl_kinetic(wvl_plan* p, const void* s, const void* k0, void* out, void* ws, void* stream) {
   if (int r = check_plan(p)) return r;
   if (!s || !out || !ws) return fail(WVL_EINVAL, "wvl_kinetic: NULL pointer");
-  if (s == out) return fail(WVL_EINVAL, "wvl_kinetic: output aliases input");
-  if (k0 == s) return fail(WVL_EINVAL, "wvl_kinetic: k0 aliases s");
+  if (int r = check_disjoint(p, s, out, "wvl_kinetic")) return r;
+  if (k0 && overlap(k0, batch_bytes(p), s, batch_bytes(p)))
+    return fail(WVL_EINVAL, "wvl_kinetic: k0 overlaps s");
+  if (k0 && k0 != out && overlap(k0, batch_bytes(p), out, batch_bytes(p)))
+    return fail(WVL_EINVAL, "wvl_kinetic: k0 overlaps out without being out");
   if (int r = check_gpu(p)) return r;
   Seq q(p, (hipStream_t)stream);
   WVL_CHK(q.pass(OP_KIN, 3, s, out, k0));
@@ -824,6 +924,8 @@ int wvl_local_hpsi(wvl_plan* p, const void* c, const double* V, double pot_scale
   if (rho && !p->shared) return fail(WVL_EUNSUPPORTED, "rho needs a WVL_SHARED_V plan");
   if (!isfinite(pot_scale) || !isfinite(kin_scale))
     return fail(WVL_EINVAL, "wvl_local_hpsi: scales must be finite");
+  if (hpsi != c && overlap(c, batch_bytes(p), hpsi, batch_bytes(p)))
+    return fail(WVL_EINVAL, "wvl_local_hpsi: hpsi overlaps c without being c");
   if (int r = check_gpu(p)) return r;
   hipStream_t st = (hipStream_t)stream;
   if (!(p->flags & WVL_USE_GRAPH))
@@ -859,6 +961,47 @@ int wvl_local_hpsi(wvl_plan* p, const void* c, const double* V, double pot_scale
   WVL_HIP(hipGraphLaunch(p->gexec, p->gstream));
   WVL_HIP(hipEventRecord(p->ev_out, p->gstream));
   WVL_HIP(hipStreamWaitEvent(st, p->ev_out, 0));
+  return WVL_OK;
+}
+
+int wvl_energy_gradient(wvl_plan* p, const void* c, const double* V, double g_loc, double g_kin,
+                        void* grad, void* ws, void* stream) {
+  if (int r = check_plan(p)) return r;
+  if (!c || !V || !grad || !ws) return fail(WVL_EINVAL, "wvl_energy_gradient: NULL pointer");
+  if (!isfinite(g_loc) || !isfinite(g_kin))
+    return fail(WVL_EINVAL, "wvl_energy_gradient: weights must be finite");
+  if (grad != c && overlap(c, batch_bytes(p), grad, batch_bytes(p)))
+    return fail(WVL_EINVAL, "wvl_energy_gradient: grad overlaps c without being c");
+  if (int r = check_gpu(p)) return r;
+  hipStream_t st = (hipStream_t)stream;
+  // 2 f_b (g_loc Hloc + g_kin Kin) c_b: with one occupation for every orbital
+  // the weights fold into the two operator scales, otherwise the orbitals are
+  // scaled by f_b afterwards
+  const double f = p->occ_uniform ? p->orbs[0].occ : 1.0;
+  if (int r = hpsi_sequence(p, st, c, V, 2.0 * f * g_loc, 2.0 * f * g_kin, grad, nullptr, nullptr,
+                            nullptr, nullptr, ws))
+    return r;
+  if (!p->occ_uniform) {
+    PassGeom g{p->d_orbs, p->d_pp, p->norb};
+    hipError_t e = launch_scale_occ(p->prec, g, p->pp[p->norb], grad, 1.0, p->elems, st);
+    if (e != hipSuccess) return hipfail(e, "occupation weights");
+  }
+  return WVL_OK;
+}
+
+int wvl_plan_query(const wvl_plan* p, int32_t what, int64_t* value) {
+  if (int r = check_plan(p)) return r;
+  if (!value) return fail(WVL_EINVAL, "value is NULL");
+  switch (what) {
+    case WVL_Q_VARIANT: *value = p->variant; break;
+    case WVL_Q_GROUP: *value = p->use_xy && p->shared ? p->xy_G : 0; break;
+    case WVL_Q_PERSISTENT: *value = p->persistent ? 1 : 0; break;
+    case WVL_Q_XDIV: *value = p->xdiv; break;
+    case WVL_Q_PGRID: *value = p->pgrid_mul; break;
+    case WVL_Q_TUNE_BEST: *value = p->tune_best; break;
+    case WVL_Q_FUSED_Z: *value = p->use_xy && p->zfuse ? 1 : 0; break;
+    default: return fail(WVL_EINVAL, "unknown query %d", what);
+  }
   return WVL_OK;
 }
 

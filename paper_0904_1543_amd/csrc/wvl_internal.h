@@ -93,6 +93,10 @@ __host__ __device__ constexpr double coef(int p, int o, int part) {
 // ---------------------------------------------------------------------------
 // Device descriptors
 // ---------------------------------------------------------------------------
+constexpr int kThreads = 256;          // threads per workgroup for the pass kernels
+constexpr int kContigLds = 4096;       // LDS values per x-pass tile
+constexpr int kHalo = 32;              // periodic halo kept on each side in LDS
+
 struct OrbDev {
   int32_t m[3];        // fine dims m1, m2, m3
   int32_t pad;
@@ -118,11 +122,16 @@ struct PassGeom {
   int32_t* queue;
   int32_t ntiles;
   int32_t grid;
+  int32_t xdiv;    // axis-1 passes: rows per tile = (rows that fit in LDS) / xdiv
 };
 
-constexpr int kThreads = 256;          // threads per workgroup for the pass kernels
-constexpr int kContigLds = 4096;       // LDS values per x-pass tile
-constexpr int kHalo = 32;              // periodic halo kept on each side in LDS
+// rows of length m1 per axis-1 tile (kContigLds values of LDS with halo)
+__host__ __device__ inline int contig_rows(int m1, int xdiv) {
+  int r = kContigLds / (m1 + 2 * kHalo);
+  r = xdiv > 1 ? r / xdiv : r;
+  return r < 1 ? 1 : r;
+}
+
 
 __device__ __forceinline__ void find_tile(const int32_t* prefix, int norb, int tile, int& b, int& t) {
   int lo = 0, hi = norb;  // prefix[lo] <= tile < prefix[hi]

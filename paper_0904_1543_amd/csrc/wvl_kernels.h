@@ -51,6 +51,10 @@ hipError_t launch_pot_orb(int prec, const PassGeom& g, int ntiles, const void* p
                           const double* V, double pot_scale, int64_t plane, double* ppart,
                           hipStream_t st);
 
+// x_b <- mul * f_b * x_b over every orbital (tiles of kThreads points, prefix g)
+hipError_t launch_scale_occ(int prec, const PassGeom& g, int ntiles, void* x, double mul,
+                            int64_t plane, hipStream_t st);
+
 // Per-orbital energies eorb[b] (potential) and eorb[norb + b] (kinetic) from
 // the tile partials; pot_mode 0: none, 1: per-orbital tiles (prefix pp),
 // 2: shared-grid blocks laid out [norb][nblk].

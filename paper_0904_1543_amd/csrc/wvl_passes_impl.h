@@ -230,7 +230,7 @@ __global__ __launch_bounds__(kThreads) void k_contig(PassGeom g, const void* in,
   const int m1 = od.m[0];
   const int rows = od.m[1] * od.m[2];
   const int pitch = m1 + 2 * kHalo;
-  const int R = max(1, kContigLds / pitch);
+  const int R = contig_rows(m1, g.xdiv);
   const int row0 = t * R;
   const int nrows = min(R, rows - row0);
   const int64_t gbase = od.off + (int64_t)row0 * m1;

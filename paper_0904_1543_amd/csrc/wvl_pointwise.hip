@@ -7,6 +7,8 @@
 //  * energies as float64 reductions (the paper calls BLAS for them, Sec. 4.1):
 //    fixed-order two-stage sums, no floating-point atomics.
 
+#include <algorithm>
+
 #include "wvl_kernels.h"
 
 namespace wvl {
@@ -46,20 +48,34 @@ __global__ __launch_bounds__(kThreads) void k_pot_orb(PassGeom g, const void* ps
                                                       double pot_scale, int64_t plane,
                                                       double* __restrict__ ppart) {
   using T = Prec<P>;
+  for_each_tile(g, [&](int b, int t, int slot) {
+    const OrbDev od = g.orbs[b];
+    const int64_t M = (int64_t)od.m[0] * od.m[1] * od.m[2];
+    const int64_t r = (int64_t)t * kThreads + threadIdx.x;
+    double e = 0.0;
+    if (r < M) {
+      const double v = V[od.voff + r];
+      const typename T::V p = T::ldc(psi, od.off + r, plane);
+      const double pd = T::d(p);
+      e = v * pd * pd;
+      if (y) T::st(y, od.off + r, plane, T::scale(p, v * pot_scale));
+    }
+    if (ppart) block_sum_store(e, ppart + slot);
+  });
+}
+
+// x_b <- mul * f_b * x_b for every orbital b (the occupation weights of the
+// energy gradient 2 f_b H c_b)
+template <int P>
+__global__ __launch_bounds__(kThreads) void k_scale_occ(PassGeom g, void* x, double mul,
+                                                        int64_t plane) {
+  using T = Prec<P>;
   int b, t;
   find_tile(g.prefix, g.norb, blockIdx.x, b, t);
   const OrbDev od = g.orbs[b];
   const int64_t M = (int64_t)od.m[0] * od.m[1] * od.m[2];
   const int64_t r = (int64_t)t * kThreads + threadIdx.x;
-  double e = 0.0;
-  if (r < M) {
-    const double v = V[od.voff + r];
-    const typename T::V p = T::ldc(psi, od.off + r, plane);
-    const double pd = T::d(p);
-    e = v * pd * pd;
-    if (y) T::st(y, od.off + r, plane, T::scale(p, v * pot_scale));
-  }
-  if (ppart) block_sum_store(e, ppart + blockIdx.x);
+  if (r < M) T::st(x, od.off + r, plane, T::scale(T::ldc(x, od.off + r, plane), mul * od.occ));
 }
 
 __device__ double block_sum_all(double v) {
@@ -178,11 +194,23 @@ hipError_t launch_pot_orb(int prec, const PassGeom& g, int ntiles, const void* p
                           const double* V, double pot_scale, int64_t plane, double* ppart,
                           hipStream_t st) {
   if (ntiles == 0) return hipSuccess;
-  dim3 grid(ntiles), block(kThreads);
+  dim3 grid(g.queue ? std::min(ntiles, g.grid) : ntiles), block(kThreads);
   switch (prec) {
     case F64: hipLaunchKernelGGL((k_pot_orb<F64>), grid, block, 0, st, g, psi, y, V, pot_scale, plane, ppart); break;
     case F32: hipLaunchKernelGGL((k_pot_orb<F32>), grid, block, 0, st, g, psi, y, V, pot_scale, plane, ppart); break;
     default:  hipLaunchKernelGGL((k_pot_orb<F32C>), grid, block, 0, st, g, psi, y, V, pot_scale, plane, ppart); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_scale_occ(int prec, const PassGeom& g, int ntiles, void* x, double mul,
+                           int64_t plane, hipStream_t st) {
+  if (ntiles == 0) return hipSuccess;
+  dim3 grid(ntiles), block(kThreads);
+  switch (prec) {
+    case F64: hipLaunchKernelGGL((k_scale_occ<F64>), grid, block, 0, st, g, x, mul, plane); break;
+    case F32: hipLaunchKernelGGL((k_scale_occ<F32>), grid, block, 0, st, g, x, mul, plane); break;
+    default:  hipLaunchKernelGGL((k_scale_occ<F32C>), grid, block, 0, st, g, x, mul, plane); break;
   }
   return hipGetLastError();
 }

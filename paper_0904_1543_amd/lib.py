@@ -20,6 +20,8 @@ WVL_OK, WVL_EINVAL, WVL_EUNSUPPORTED, WVL_ENOMEM, WVL_EHIP, WVL_ETIMEOUT, WVL_EN
     0, -1, -2, -3, -4, -5, -6
 WVL_F64, WVL_F32, WVL_F32C = 0, 1, 2
 WVL_SHARED_V, WVL_USE_GRAPH, WVL_PERSISTENT, WVL_AUTOTUNE = 1, 2, 4, 8
+(WVL_Q_VARIANT, WVL_Q_GROUP, WVL_Q_PERSISTENT, WVL_Q_XDIV, WVL_Q_PGRID, WVL_Q_TUNE_BEST,
+ WVL_Q_FUSED_Z) = range(7)
 
 STATUS_NAMES = {0: "WVL_OK", -1: "WVL_EINVAL", -2: "WVL_EUNSUPPORTED", -3: "WVL_ENOMEM",
                 -4: "WVL_EHIP", -5: "WVL_ETIMEOUT", -6: "WVL_ENODEV"}
@@ -68,6 +70,8 @@ _SIGS = {
     "wvl_convert": [P, P, I32, P, I32, I64, P],
     "wvl_plan_sync": [P, P],
     "wvl_plan_tuning": [P, ctypes.POINTER(I32), DP, I32],
+    "wvl_plan_query": [P, I32, ctypes.POINTER(I64)],
+    "wvl_energy_gradient": [P, P, P, D, D, P, P, P],
     "wvl_plan_profile": [P, I32],
     "wvl_plan_profile_read": [P, ctypes.POINTER(I32), DP, I32, ctypes.POINTER(I32)],
 }

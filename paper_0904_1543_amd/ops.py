@@ -197,6 +197,19 @@ class Plan:
                            ptr(r), e_loc, e_kin, ptr(eo), ptr(self.ws), stream_handle())
         return dict(hpsi=out, rho=r, energies=e, e_orb=eo)
 
+    def energy_gradient(self, c, V, g_loc=1.0, g_kin=1.0, out=None):
+        """2 f_b (g_loc Hloc + g_kin Kin) c_b for every orbital (on the device)."""
+        out = self.empty() if out is None else out
+        lib.wvl_energy_gradient(self.h, ptr(c), ptr(V), float(g_loc), float(g_kin), ptr(out),
+                                ptr(self.ws), stream_handle())
+        return out
+
+    def query(self, what):
+        """A plan property (lib.WVL_Q_*)."""
+        v = ctypes.c_int64()
+        lib.wvl_plan_query(self.h, int(what), ctypes.byref(v))
+        return v.value
+
     def overlap(self, c):
         S = torch.empty((self.norb, self.norb), dtype=torch.float64, device=self.dev)
         lib.wvl_overlap(self.h, ptr(c), ptr(S), ptr(self.ws), stream_handle())

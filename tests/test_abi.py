@@ -103,7 +103,7 @@ def test_plan_sizes(dry):
 def test_calls_check_arguments_before_gpu(dry):
     rc, p = _plan(dry, [(4, 4, 4)] * 2)
     assert rc == lib.WVL_OK
-    a, b, ws = ctypes.c_void_p(0x1000), ctypes.c_void_p(0x2000), ctypes.c_void_p(0x3000)
+    a, b, ws = ctypes.c_void_p(0x100000), ctypes.c_void_p(0x200000), ctypes.c_void_p(0x300000)
     f = lib.raw
     # NULL pointers and aliasing -> EINVAL
     assert f("wvl_synthesis")(p, None, b, ws, None) == lib.WVL_EINVAL
@@ -129,9 +129,64 @@ def test_calls_check_arguments_before_gpu(dry):
 
 def test_unsupported_combinations(dry):
     rc, p = _plan(dry, [(4, 4, 4), (4, 6, 4)], flags=0)    # uneven, per-orbital V
-    a, b, ws = ctypes.c_void_p(0x1000), ctypes.c_void_p(0x2000), ctypes.c_void_p(0x3000)
+    a, b, ws = ctypes.c_void_p(0x100000), ctypes.c_void_p(0x200000), ctypes.c_void_p(0x300000)
     assert lib.raw("wvl_local_density")(p, a, b, 0, ws, None) == lib.WVL_EUNSUPPORTED
     assert lib.raw("wvl_overlap")(p, a, b, ws, None) == lib.WVL_EUNSUPPORTED
     assert lib.raw("wvl_local_hpsi")(p, a, a, 1.0, 1.0, b, b, None, None, None, ws, None) == \
         lib.WVL_EUNSUPPORTED   # rho needs a shared potential
+    lib.wvl_plan_destroy(p)
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2])
+def test_partial_overlap_is_rejected(dry, prec):
+    """Batch arrays of 2 x 8^3 elements (8 KiB in float64 and compensated
+    float32, 4 KiB in float32): an output that starts inside its input is
+    rejected; hpsi (or the gradient) equal to c is allowed."""
+    rc, p = _plan(dry, [(4, 4, 4)] * 2, prec=prec)
+    assert rc == lib.WVL_OK
+    f = lib.raw
+    a, V, ws = 0x100000, ctypes.c_void_p(0x200000), ctypes.c_void_p(0x300000)
+    A = ctypes.c_void_p(a)
+    inside = ctypes.c_void_p(a + 8)
+    nbytes = 2 * 512 * (4 if prec == 1 else 8)
+    after = ctypes.c_void_p(a + nbytes)      # first byte past the array: disjoint
+    hpsi = f("wvl_local_hpsi")
+    assert hpsi(p, A, V, 1.0, 1.0, inside, None, None, None, None, ws, None) == lib.WVL_EINVAL
+    assert "overlaps" in lib.wvl_last_error()
+    assert hpsi(p, A, V, 1.0, 1.0, A, None, None, None, None, ws, None) == lib.WVL_ENODEV
+    assert hpsi(p, A, V, 1.0, 1.0, after, None, None, None, None, ws, None) == lib.WVL_ENODEV
+    grad = f("wvl_energy_gradient")
+    assert grad(p, A, V, 1.0, 1.0, inside, ws, None) == lib.WVL_EINVAL
+    assert grad(p, A, V, 1.0, 1.0, A, ws, None) == lib.WVL_ENODEV
+    assert f("wvl_synthesis")(p, A, inside, ws, None) == lib.WVL_EINVAL
+    assert f("wvl_analysis")(p, inside, A, ws, None) == lib.WVL_EINVAL
+    assert f("wvl_magic_filter")(p, A, inside, 1, ws, None) == lib.WVL_EINVAL
+    out = ctypes.c_void_p(0x400000)
+    k0_inside_out = ctypes.c_void_p(0x400000 + 16)
+    assert f("wvl_kinetic")(p, A, k0_inside_out, out, ws, None) == lib.WVL_EINVAL
+    assert f("wvl_kinetic")(p, A, out, out, ws, None) == lib.WVL_ENODEV
+    assert f("wvl_kinetic")(p, A, inside, out, ws, None) == lib.WVL_EINVAL
+    lib.wvl_plan_destroy(p)
+
+
+def test_plan_queries(dry):
+    rc, p = _plan(dry, [(8, 6, 32)] * 33)        # fine (16, 12, 64): G = 2
+    assert rc == lib.WVL_OK
+    v = ctypes.c_int64()
+    q = lib.raw("wvl_plan_query")
+    assert q(p, lib.WVL_Q_VARIANT, ctypes.byref(v)) == lib.WVL_OK and v.value == 2
+    assert q(p, lib.WVL_Q_GROUP, ctypes.byref(v)) == lib.WVL_OK and v.value == 2
+    assert q(p, lib.WVL_Q_PERSISTENT, ctypes.byref(v)) == lib.WVL_OK and v.value == 0
+    assert q(p, lib.WVL_Q_XDIV, ctypes.byref(v)) == lib.WVL_OK and v.value == 1
+    assert q(p, lib.WVL_Q_PGRID, ctypes.byref(v)) == lib.WVL_OK and v.value == 8
+    assert q(p, lib.WVL_Q_TUNE_BEST, ctypes.byref(v)) == lib.WVL_OK and v.value == -1
+    assert q(p, lib.WVL_Q_FUSED_Z, ctypes.byref(v)) == lib.WVL_OK and v.value == 1
+    assert q(p, 99, ctypes.byref(v)) == lib.WVL_EINVAL
+    assert q(p, lib.WVL_Q_GROUP, None) == lib.WVL_EINVAL
+    lib.wvl_plan_destroy(p)
+    rc, p = _plan(dry, [(8, 6, 32)] * 33, prec=2, flags=4)   # per-orbital V, persistent
+    assert q(p, lib.WVL_Q_VARIANT, ctypes.byref(v)) == lib.WVL_OK and v.value == 1
+    assert q(p, lib.WVL_Q_GROUP, ctypes.byref(v)) == lib.WVL_OK and v.value == 0
+    assert q(p, lib.WVL_Q_PERSISTENT, ctypes.byref(v)) == lib.WVL_OK and v.value == 1
+    assert q(p, lib.WVL_Q_FUSED_Z, ctypes.byref(v)) == lib.WVL_OK and v.value == 0
     lib.wvl_plan_destroy(p)

@@ -15,6 +15,7 @@ import pytest
 import torch
 
 from oracle import wavelet as W
+from parity_helpers import assert_close, assert_scalar
 from paper_0904_1543_amd import inputs, lib, ops
 
 pytestmark = pytest.mark.gpu
@@ -22,22 +23,13 @@ pytestmark = pytest.mark.gpu
 TOL = {"f64": 1e-12, "f32": 2e-6, "f32c": 1e-10}
 
 
-def _rel(a, b):
-    a = np.asarray(a, dtype=np.float64).ravel()
-    b = np.asarray(b, dtype=np.float64).ravel()
-    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
-
-
-def _batch_rel(got, ref):
-    num = sum(np.sum((np.asarray(g) - np.asarray(r)) ** 2) for g, r in zip(got, ref))
-    den = sum(np.sum(np.asarray(r) ** 2) for r in ref)
-    return float(np.sqrt(num / den))
+NCAND = 12   # tuner candidates: 4 launch sequences x 3 tile shapes
 
 
 def _tuning(plan):
     v = ctypes.c_int32()
-    t = (ctypes.c_double * 4)()
-    lib.wvl_plan_tuning(plan.h, ctypes.byref(v), t, 4)
+    t = (ctypes.c_double * NCAND)()
+    lib.wvl_plan_tuning(plan.h, ctypes.byref(v), t, NCAND)
     return v.value, list(t)
 
 
@@ -52,11 +44,11 @@ def test_persistent_uneven_matches_oracle(prec):
     c, Vt = plan.pack(cs["C"]), plan.pack_potential(cs["V"])
     r = _hpsi(plan, c, Vt)
     ref = [W.local_hpsi_orbital(x, v)[0] for x, v in zip(cs["C"], cs["V"])]
-    assert _batch_rel(plan.unpack(r["hpsi"]), ref) < TOL[prec]
+    assert_close(plan.unpack(r["hpsi"]), ref, TOL[prec])
     ref_e = W.local_hpsi(cs["C"], cs["V"], cs["occ"], shared_v=False)
     eo = r["e_orb"].cpu().numpy()
-    assert _rel(eo[: plan.norb], ref_e["e_loc_orb"]) < TOL[prec]
-    assert _rel(eo[plan.norb:], ref_e["e_kin_orb"]) < TOL[prec]
+    assert_close(eo[: plan.norb], ref_e["e_loc_orb"], TOL[prec])
+    assert_close(eo[plan.norb:], ref_e["e_kin_orb"], TOL[prec])
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32c"])
@@ -100,28 +92,65 @@ def test_autotune_picks_a_timed_candidate(prec):
     plan = ops.Plan(cs["dims"], prec=prec, autotune=True)
     variant, times = _tuning(plan)
     measured = [t for t in times if t >= 0]
-    assert times[0] > 0 and times[1] > 0 and len(measured) >= 3
+    # pass-by-pass in two axis-1 tile shapes, the plane kernel at two
+    # occupancies (and the float64 vector engine); no persistent shapes
+    assert times[0] > 0 and times[1] > 0 and times[3] > 0 and times[6] > 0
+    assert len(measured) == (5 if prec == "f64" else 4)
+    assert all(times[k] < 0 for k in (2, 4, 5, 7, 8, 10, 11))
     assert variant in (0, 1, 2)
     # the kept candidate is the fastest one measured
     best = int(np.argmin([t if t >= 0 else np.inf for t in times]))
-    expect = {0: 0, 1: 2 if prec == "f64" else 1, 2: 2 if prec == "f64" else 1, 3: 1}[best]
+    assert plan.query(lib.WVL_Q_TUNE_BEST) == best
+    seq = best // 3
+    expect = {0: 0, 1: 2 if prec == "f64" else 1, 2: 2 if prec == "f64" else 1, 3: 1}[seq]
     assert variant == expect
+    assert plan.query(lib.WVL_Q_XDIV) == (2 if best == 1 else 1)
     r = plan.local_hpsi(plan.pack(cs["C"]), plan.pack_potential(cs["V"]), per_orbital=True)
     ref = W.local_hpsi(cs["C"], cs["V"], cs["occ"])
-    assert _batch_rel(plan.unpack(r["hpsi"]), list(ref["hpsi"])) < TOL[prec]
+    assert_close(plan.unpack(r["hpsi"]), list(ref["hpsi"]), TOL[prec])
 
 
 def test_untuned_plan_reports_no_times():
     cs = inputs.random_case(55, 2, (6, 6, 6))
     plan = ops.Plan(cs["dims"], prec="f64")
     _, times = _tuning(plan)
-    assert times == [-1.0] * 4
+    assert times == [-1.0] * NCAND
+    assert plan.query(lib.WVL_Q_TUNE_BEST) == -1
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "f32c"])
+@pytest.mark.parametrize("mode", ["plain", "persistent", "graph"])
+def test_pass_by_pass_per_orbital_potential(prec, mode, monkeypatch):
+    """The pass-by-pass sequence with one potential per orbital (its pointwise
+    stage is the per-orbital kernel), eager, persistent and graph-replayed."""
+    monkeypatch.setenv("WVL_NO_PLANE_KERNEL", "1")
+    cs = inputs.random_uneven_case(56, 11, lo=2, hi=22)
+    plan = ops.Plan(cs["dims"], prec=prec, shared_v=False, persistent=(mode != "plain"),
+                    graph=(mode == "graph"))
+    assert plan.query(lib.WVL_Q_VARIANT) == 0
+    assert plan.query(lib.WVL_Q_PERSISTENT) == (mode != "plain")
+    c, Vt = plan.pack(cs["C"]), plan.pack_potential(cs["V"])
+    ref = W.local_hpsi(cs["C"], cs["V"], cs["occ"], shared_v=False)
+    for rep in range(2 if mode == "graph" else 1):
+        r = _hpsi(plan, c, Vt)
+        assert_close(plan.unpack(r["hpsi"]), ref["hpsi"], TOL[prec], f"hpsi (call {rep})")
+        eo = r["e_orb"].cpu().numpy()
+        assert_close(eo[: plan.norb], ref["e_loc_orb"], TOL[prec], "e_pot per orbital")
+        assert_close(eo[plan.norb:], ref["e_kin_orb"], TOL[prec], "e_kin per orbital")
+        e = r["energies"].cpu().numpy()
+        assert_scalar(e[0], float(np.sum(cs["occ"] * ref["e_loc_orb"])), TOL[prec], "E_loc")
+        assert_scalar(e[1], ref["e_kin"], TOL[prec], "E_kin")
 
 
 def test_uneven_512_orbital_batch_f32c_persistent_graph():
+    """The 512-orbital batch through the launch sequence the tuner picks."""
     wl = inputs.workload(5)
     dims = wl["dims"]
-    plan = ops.Plan(dims, prec="f32c", shared_v=False, persistent=True, graph=True)
+    plan = ops.Plan(dims, prec="f32c", shared_v=False, persistent=True, graph=True,
+                    autotune=True)
+    print(f"tuner kept candidate {plan.query(lib.WVL_Q_TUNE_BEST)}, "
+          f"variant {plan.query(lib.WVL_Q_VARIANT)}", flush=True)
+    assert plan.query(lib.WVL_Q_PERSISTENT) == 1
     c = plan.pack(wl["C"])
     Vt = plan.pack_potential(wl["V"])
     out = plan.empty()
@@ -137,12 +166,11 @@ def test_uneven_512_orbital_batch_f32c_persistent_graph():
         o, m = int(plan.offsets[b]), plan.M[b]
         g = got[o:o + m].cpu().numpy().reshape(inputs.fine_shape(dims[b]))
         ref = W.local_hpsi_orbital(wl["C"][b], wl["V"][b])[0]
-        err = _rel(g, ref)
-        print(f"orbital {b} dims {dims[b]}: rel err {err:.2e}", flush=True)
-        assert err < TOL["f32c"]
+        print(f"orbital {b} dims {dims[b]}", flush=True)
+        assert_close(g, ref, TOL["f32c"], f"orbital {b}")
     # every orbital's energies against the float64 plan (itself within 1e-12 of the oracle)
     del out
     ref64 = ops.Plan(dims, prec="f64", shared_v=False)
     c64 = plan.to_f64(c)
     r64 = ref64.local_hpsi(c64, Vt, rho=False, per_orbital=True)
-    assert _rel(eo.cpu().numpy(), r64["e_orb"].cpu().numpy()) < TOL["f32c"]
+    assert_close(eo.cpu().numpy(), r64["e_orb"].cpu().numpy(), TOL["f32c"])
