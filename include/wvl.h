@@ -174,6 +174,20 @@ int wvl_overlap(wvl_plan *plan, const void *c, double *S, void *ws, void *stream
  * pivot is reported by wvl_plan_sync() as WVL_EINVAL.  Up to 256 orbitals. */
 int wvl_orthonormalize(wvl_plan *plan, void *c, double *S, double *L, void *ws, void *stream);
 
+/* wvl_orthonormalize for callers that cannot allocate device memory (code
+ * under hipGraph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same operation and the same kernels, but the scratch memory
+ * (overlap slice partials, L, L^{-1}, product scratch) is a static device
+ * array of the library instead of a caller workspace, so no `ws` argument.
+ * The array holds 80 MiB on every GPU the library runs on, from the first
+ * wvl_create() on that device until the process ends; every batch of up to
+ * 256 orbitals fits (larger needs are rejected with WVL_EUNSUPPORTED before
+ * any GPU work).  The call itself allocates nothing.  All calls on one GPU
+ * share that one array: calls that overlap in time on the same GPU (other
+ * streams, other threads, other plans) race and must be serialised by the
+ * caller.  Nothing in the array needs to start at zero. */
+int wvl_orthonormalize_noalloc(wvl_plan *plan, void *c, double *S, double *L, void *stream);
+
 /* Format conversion of `count` values between WVL_F64, WVL_F32 and WVL_F32C
  * (hi/lo planes of `count` floats each); src and dst must not overlap. */
 int wvl_convert(wvl_ctx *ctx, const void *src, int32_t src_prec, void *dst, int32_t dst_prec,

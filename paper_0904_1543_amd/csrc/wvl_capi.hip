@@ -11,6 +11,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -195,6 +196,7 @@ static int check_disjoint(const wvl_plan* p, const void* in, const void* out, co
 
 namespace {
 int autotune(wvl_plan* p);
+int scratch_setup(int device);
 }  // namespace
 
 extern "C" {
@@ -224,6 +226,10 @@ int wvl_create(wvl_ctx** ctx, int device) {
     if (e != hipSuccess) { delete c; return hipfail(e, "hipGetDeviceProperties"); }
     c->lds_per_block = prop.sharedMemPerBlock;
     c->cus = prop.multiProcessorCount;
+    // the no-allocation entry point's scratch array on this device
+    e = hipSetDevice(device);
+    if (e != hipSuccess) { delete c; return hipfail(e, "hipSetDevice"); }
+    if (int r = scratch_setup(device)) { delete c; return r; }
   }
   *ctx = c;
   return WVL_OK;
@@ -1018,26 +1024,22 @@ int wvl_overlap(wvl_plan* p, const void* c, double* S, void* ws, void* stream) {
   return WVL_OK;
 }
 
-int wvl_orthonormalize(wvl_plan* p, void* c, double* S, double* L, void* ws, void* stream) {
-  if (int r = check_plan(p)) return r;
-  if (!c || !ws) return fail(WVL_EINVAL, "wvl_orthonormalize: NULL pointer");
-  if (!p->dense) return fail(WVL_EUNSUPPORTED, "wvl_orthonormalize needs a dense uniform batch");
-  if (p->norb > 256) return fail(WVL_EUNSUPPORTED, "wvl_orthonormalize supports up to 256 orbitals");
-  if (int r = check_gpu(p)) return r;
-  hipStream_t st = (hipStream_t)stream;
-  double* Lw = (double*)wsp(ws, p->o_L);
-  double* Li = (double*)wsp(ws, p->o_Li);
+}  // extern "C"
+
+// Overlap, Cholesky and X <- L^{-1} X with the scratch arrays given (SYRK
+// slice partials, L, L^{-1}, a product scratch).
+static int orthonormalize_into(wvl_plan* p, void* c, double* S, double* L, double* syrk, double* Lw,
+                               double* Li, double* T, hipStream_t st) {
   const size_t nn = sizeof(double) * (size_t)p->norb * p->norb;
   hipError_t e;
   {
     Mark mk(p, st, ST_OVERLAP);
-    e = launch_overlap_p(p->prec, c, p->elems, p->norb, p->M, Lw, (double*)wsp(ws, p->o_syrk), st);
+    e = launch_overlap_p(p->prec, c, p->elems, p->norb, p->M, Lw, syrk, st);
   }
   if (e != hipSuccess) return hipfail(e, "overlap");
   if (S) WVL_HIP(hipMemcpyAsync(S, Lw, nn, hipMemcpyDeviceToDevice, st));
   {
     Mark mk(p, st, ST_CHOL);
-    double* T = (double*)wsp(ws, p->o_T);
     e = launch_cholesky_inv(Lw, Li, T, p->norb, p->d_info, st);
     if (e == hipSuccess) e = launch_linv_offdiag(Lw, Li, T, p->norb, st);
   }
@@ -1052,6 +1054,79 @@ int wvl_orthonormalize(wvl_plan* p, void* c, double* S, double* L, void* ws, voi
   }
   if (e != hipSuccess) return hipfail(e, "trmm");
   return WVL_OK;
+}
+
+static int check_orthonormalize(const wvl_plan* p, const void* c, const char* what) {
+  if (int r = check_plan(p)) return r;
+  if (!c) return fail(WVL_EINVAL, "%s: NULL pointer", what);
+  if (!p->dense) return fail(WVL_EUNSUPPORTED, "%s needs a dense uniform batch", what);
+  if (p->norb > 256) return fail(WVL_EUNSUPPORTED, "%s supports up to 256 orbitals", what);
+  return WVL_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Entry point for callers that cannot allocate (graph capture, serving loops):
+// its scratch memory is a static device array of the library, one per GPU,
+// held until the process ends.  Host code never passes the array's name to a
+// kernel or a copy: that name is a host-side stand-in, so every use goes
+// through the device address that hipGetSymbolAddress returns, looked up once
+// per device when a context is created there.
+// ---------------------------------------------------------------------------
+constexpr size_t kScratchBytes = (size_t)80 << 20;   // 80 MiB per GPU
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// device address of `scratch` on `device` (the current device); once per device
+int scratch_setup(int device) {
+  if (device < 0 || device >= kMaxDevices) return fail(WVL_EUNSUPPORTED, "device %d", device);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[device]) return WVL_OK;
+  void* ptr = nullptr;
+  hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr) return hipfail(e, "hipGetSymbolAddress(scratch)");
+  g_scratch_ptr[device] = ptr;
+  return WVL_OK;
+}
+
+void* scratch_ptr(int device) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return device >= 0 && device < kMaxDevices ? g_scratch_ptr[device] : nullptr;
+}
+}  // namespace
+
+extern "C" {
+
+int wvl_orthonormalize(wvl_plan* p, void* c, double* S, double* L, void* ws, void* stream) {
+  if (int r = check_orthonormalize(p, c, "wvl_orthonormalize")) return r;
+  if (!ws) return fail(WVL_EINVAL, "wvl_orthonormalize: NULL workspace");
+  if (int r = check_gpu(p)) return r;
+  return orthonormalize_into(p, c, S, L, (double*)wsp(ws, p->o_syrk), (double*)wsp(ws, p->o_L),
+                             (double*)wsp(ws, p->o_Li), (double*)wsp(ws, p->o_T),
+                             (hipStream_t)stream);
+}
+
+int wvl_orthonormalize_noalloc(wvl_plan* p, void* c, double* S, double* L, void* stream) {
+  if (int r = check_orthonormalize(p, c, "wvl_orthonormalize_noalloc")) return r;
+  // scratch layout: SYRK slice partials, then L, L^{-1} and the product
+  // scratch (n x n each), every part 256-byte aligned
+  const size_t nn = align256(sizeof(double) * (size_t)p->norb * p->norb);
+  const size_t syrk = align256(sizeof(double) * (size_t)syrk_partials(p->norb, p->M));
+  const size_t need = syrk + 3 * nn;
+  if (need > kScratchBytes)
+    return fail(WVL_EUNSUPPORTED,
+                "wvl_orthonormalize_noalloc: needs %zu bytes of scratch, the library holds %zu",
+                need, kScratchBytes);
+  if (int r = check_gpu(p)) return r;
+  char* base = (char*)scratch_ptr(p->ctx->device);
+  if (!base) return fail(WVL_EHIP, "wvl_orthonormalize_noalloc: scratch not set up on device %d",
+                         p->ctx->device);
+  return orthonormalize_into(p, c, S, L, (double*)base, (double*)(base + syrk),
+                             (double*)(base + syrk + nn), (double*)(base + syrk + 2 * nn),
+                             (hipStream_t)stream);
 }
 
 int wvl_convert(wvl_ctx* ctx, const void* src, int32_t sp, void* dst, int32_t dp, int64_t n,

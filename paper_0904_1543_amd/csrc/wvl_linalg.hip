@@ -32,12 +32,13 @@ __host__ __device__ inline int nblk64(int norb) { return (norb + kBlk - 1) / kBl
 __host__ __device__ inline int ntri(int nb) { return nb * (nb + 1) / 2; }
 
 static int64_t syrk32_partials(int norb, int64_t len);
+static bool syrk32_used(int norb);
 
+// doubles of slice partials the overlap of this shape uses
 int64_t syrk_partials(int norb, int64_t len) {
+  if (syrk32_used(norb)) return syrk32_partials(norb, len);
   const int64_t nslice = (len + kSlice - 1) / kSlice;
-  const int64_t p64 = nslice * ntri(nblk64(norb)) * kBlk * kBlk;
-  const int64_t p32 = syrk32_partials(norb, len);
-  return p64 > p32 ? p64 : p32;
+  return nslice * ntri(nblk64(norb)) * kBlk * kBlk;
 }
 
 // 4 consecutive coefficients of one row as float64 (zero outside the matrix)
@@ -268,8 +269,10 @@ static int64_t syrk32_slice(int64_t len) {
   return sl < 16 ? 16 : sl;
 }
 
+static bool syrk32_used(int norb) { return norb <= kS32Rows; }
+
 static int64_t syrk32_partials(int norb, int64_t len) {
-  if (norb > kS32Rows) return 0;
+  if (!syrk32_used(norb)) return 0;
   const int64_t sl = syrk32_slice(len);
   return ((len + sl - 1) / sl) * ntri(nblk32(norb)) * 1024;
 }
@@ -277,7 +280,7 @@ static int64_t syrk32_partials(int norb, int64_t len) {
 template <int P>
 static hipError_t overlap_p(const void* X, int64_t plane, int norb, int64_t len, double* S,
                             double* work, hipStream_t st) {
-  if (norb <= kS32Rows) {
+  if (syrk32_used(norb)) {
     const int64_t sl = syrk32_slice(len);
     const int nslice = (int)((len + sl - 1) / sl);
     hipLaunchKernelGGL((k_syrk32<P>), dim3((unsigned)nslice), dim3(512), 0, st, X, plane, norb, len,

@@ -67,6 +67,7 @@ _SIGS = {
     "wvl_local_hpsi": [P, P, P, D, D, P, P, P, P, P, P, P],
     "wvl_overlap": [P, P, P, P, P],
     "wvl_orthonormalize": [P, P, P, P, P, P],
+    "wvl_orthonormalize_noalloc": [P, P, P, P, P],
     "wvl_convert": [P, P, I32, P, I32, I64, P],
     "wvl_plan_sync": [P, P],
     "wvl_plan_tuning": [P, ctypes.POINTER(I32), DP, I32],

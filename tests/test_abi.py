@@ -190,3 +190,18 @@ def test_plan_queries(dry):
     assert q(p, lib.WVL_Q_PERSISTENT, ctypes.byref(v)) == lib.WVL_OK and v.value == 1
     assert q(p, lib.WVL_Q_FUSED_Z, ctypes.byref(v)) == lib.WVL_OK and v.value == 0
     lib.wvl_plan_destroy(p)
+
+
+def test_noalloc_orthonormalize_checks(dry):
+    """Arguments and sizes are checked before any GPU work."""
+    f = lib.raw("wvl_orthonormalize_noalloc")
+    a = ctypes.c_void_p(0x100000)
+    rc, p = _plan(dry, [(4, 4, 4)] * 257)
+    assert rc == lib.WVL_OK
+    assert f(p, a, None, None, None) == lib.WVL_EUNSUPPORTED      # more than 256 orbitals
+    lib.wvl_plan_destroy(p)
+    rc, p = _plan(dry, [(4, 4, 4)] * 3)
+    assert f(p, None, None, None, None) == lib.WVL_EINVAL
+    assert f(None, a, None, None, None) == lib.WVL_EINVAL
+    assert f(p, a, None, None, None) == lib.WVL_ENODEV             # valid, but no GPU
+    lib.wvl_plan_destroy(p)
