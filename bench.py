@@ -240,6 +240,63 @@ def errors_vs_oracle(got, energies, ref):
             "e_kin_orb": pair(eo[n:], ref["e_kin_orb"])}
 
 
+PRECOND_ITERS = 5
+
+
+def run_precond(C, dims, steps, warmup, check):
+    """The preconditioner (Sec. 2, Eq. "precon") on the same batch: 5 steps of
+    preconditioned conjugate gradients per call, float64 and compensated
+    float32, the combined-filter form and the separate-pass form of the
+    paper's GPU design.  Inputs: the batch's coefficients as gradients, one
+    orbital energy per orbital uniform in [-1, -0.1]."""
+    import torch
+    from paper_0904_1543_amd import inputs, ops
+
+    norb = len(dims)
+    pts = norb * int(np.prod(inputs.fine_shape(dims[0])))
+    eps = -inputs.rng_for(31).uniform(0.1, 1.0, size=norb)
+    out = {"workload": f"{norb} orbitals, coarse 48^3 (fine 96^3), {PRECOND_ITERS} conjugate-"
+                       "gradient steps per call, eps_b uniform in [-1, -0.1]",
+           "iters": PRECOND_ITERS}
+    sample = [0, norb - 1]
+    refs = None
+    if check:
+        from oracle import precond as PC
+        refs = {b: PC.pcg(C[b], eps[b], PRECOND_ITERS)[0] for b in sample}
+    for prec in ("f64", "f32c"):
+        plan = ops.Plan(dims, prec=prec)
+        g = plan.pack(C)
+        gt = plan.empty()
+        for form, sep in (("combined_filter", False), ("separate_passes", True)):
+            for _ in range(max(1, warmup)):
+                plan.precondition(g, eps, PRECOND_ITERS, separate=sep, out=gt)
+            torch.cuda.synchronize()
+            t0 = torch.cuda.Event(enable_timing=True)
+            t1 = torch.cuda.Event(enable_timing=True)
+            t0.record()
+            for _ in range(steps):
+                plan.precondition(g, eps, PRECOND_ITERS, separate=sep, out=gt)
+            t1.record()
+            torch.cuda.synchronize()
+            ms = t0.elapsed_time(t1) / steps
+            rec = {"ms_per_call": ms, "ms_per_cg_step": ms / PRECOND_ITERS,
+                   "orbital_gridpoints_per_s_per_step": pts / (ms / PRECOND_ITERS * 1e-3)}
+            if refs is not None:
+                got = plan.to_f64(gt)
+                M = plan.M[0]
+                num = den = 0.0
+                for b in sample:
+                    d = got[b * M:(b + 1) * M].cpu().numpy().reshape(refs[b].shape) - refs[b]
+                    num += float(np.sum(d * d))
+                    den += float(np.sum(refs[b] ** 2))
+                rec["rel_err_vs_oracle"] = {"orbitals": sample, "normwise": (num / den) ** 0.5,
+                                            "tolerance": TOL[prec]}
+            out[f"{prec}/{form}"] = rec
+        del plan, g, gt
+        torch.cuda.empty_cache()
+    return out
+
+
 def run_uneven(steps, warmup):
     """The 512-orbital uneven batch, compensated float32, persistent launches
     in a replayed hipGraph, launch sequence chosen by the tuner."""
@@ -356,6 +413,9 @@ def main():
                                       not args.no_cpu_baseline)
         torch.cuda.empty_cache()
 
+    print("[bench] preconditioner", file=sys.stderr, flush=True)
+    precond = run_precond(C, dims, max(3, args.steps // 4), 1, not args.no_cpu_baseline)
+
     uneven = None
     if not args.no_uneven:
         print("[bench] uneven batch: 512 orbitals, f32c, persistent + graph + tuner",
@@ -449,6 +509,7 @@ def main():
                                               key=lambda kv: -kv[1]["total_ms_per_step"])}}
             for p, v in results.items()},
         "uneven_batch": uneven,
+        "preconditioner": precond,
     }
     print(json.dumps(line))
 

@@ -164,6 +164,34 @@ int wvl_local_hpsi(wvl_plan *plan, const void *c, const double *V, double pot_sc
 int wvl_energy_gradient(wvl_plan *plan, const void *c, const double *V, double g_loc,
                         double g_kin, void *grad, void *ws, void *stream);
 
+/* Preconditioner (Sec. 2, Eq. "precon"): for every orbital b, the
+ * preconditioned gradient gt_b approximately solves the Helmholtz equation
+ *     (-1/2 nabla^2 - eps_b) gt_b = g_b
+ * in the wavelet basis, where the operator is A Kin S - eps_b I: the kinetic
+ * recursion with K_0 = -eps_b s (Sec. 3.4, last sentence) followed by the
+ * analysis.  It runs `iters` steps (0..10000) of preconditioned conjugate
+ * gradients from gt_b = 0, with the diagonal of the operator in the wavelet
+ * basis as preconditioner (one kinetic value per axis for scaling and one
+ * for wavelet coefficients, minus eps_b); a step with no positive curvature
+ * leaves gt_b unchanged.  Every eps_b must be negative (a bound orbital: the
+ * operator is then positive definite), else WVL_EINVAL.
+ *   g     batch array of the plan (read only)
+ *   eps   HOST array of norb doubles, copied before the call returns
+ *   mode  0: the operator as one combined filter per axis (synthesis,
+ *         kinetic filter and analysis composed, Sec. 2.4 last paragraph and
+ *         Sec. 6.1: the fused form); WVL_PRECOND_SEPARATE: the separate 3D
+ *         synthesis, kinetic (with K_0) and analysis passes of the paper's
+ *         GPU design (Sec. 2.4, Sec. 3.4)
+ *   gt    output batch array, must not overlap g (WVL_EINVAL)
+ *   res   nullable device array of norb doubles: the residual norm
+ *         ||g_b - H gt_b|| of the recurrence after the last step
+ * The convolution passes run in the plan's precision; the CG vector updates
+ * and scalars in float64.  Ordinary (not persistent) launches; not recorded
+ * in the plan's graph. */
+#define WVL_PRECOND_SEPARATE 1u
+int wvl_precondition(wvl_plan *plan, const void *g, const double *eps, int32_t iters,
+                     uint32_t mode, void *gt, double *res, void *ws, void *stream);
+
 /* Overlap matrix S_ij = <c_i, c_j> over all coefficients (Sec. 2.6; Sec. 5
  * step VIII), norb x norb float64, row-major.  Dense batches only. */
 int wvl_overlap(wvl_plan *plan, const void *c, double *S, void *ws, void *stream);

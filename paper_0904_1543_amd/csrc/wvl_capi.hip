@@ -77,7 +77,7 @@ struct wvl_plan {
   int64_t elems = 0;     // elements per packed plane
   int64_t vlen = 0;      // minimal length of a per-orbital V buffer
   std::vector<OrbDev> orbs;
-  std::vector<int32_t> pz, py, px, pp, pq;
+  std::vector<int32_t> pz, py, px, pp, pq, pc;
   int nblk = 0;          // 256-point blocks of the shared grid
   // plane-resident path of wvl_local_hpsi
   bool use_xy = false;
@@ -102,11 +102,12 @@ struct wvl_plan {
   int32_t* d_pp = nullptr;
   int32_t* d_pq = nullptr;
   int32_t *d_perm_z = nullptr, *d_order_z = nullptr, *d_perm_q = nullptr, *d_order_q = nullptr;
+  int32_t *d_pc = nullptr;   // preconditioner element tiles
   int32_t *d_px2 = nullptr, *d_perm_y = nullptr, *d_order_y = nullptr, *d_perm_x = nullptr,
           *d_order_x = nullptr, *d_order_x2 = nullptr, *d_perm_p = nullptr, *d_order_p = nullptr;
   int* d_info = nullptr;
   // workspace layout (byte offsets)
-  size_t ws = 0, o_A = 0, o_B = 0, o_S = 0, o_ez = 0, o_ey = 0, o_ex = 0, o_pp = 0, o_rv = 0,
+  size_t ws = 0, o_A = 0, o_B = 0, o_S = 0, o_D = 0, o_cg = 0, o_ez = 0, o_ey = 0, o_ex = 0, o_pp = 0, o_rv = 0,
          o_rho = 0, o_eorb = 0, o_syrk = 0, o_L = 0, o_Li = 0, o_T = 0, o_rhop = 0, o_epl = 0,
          o_kpl = 0, o_queue = 0;
   // graph cache
@@ -126,7 +127,7 @@ struct wvl_plan {
 
 // Stage ids for profiling: 1D passes are op * 3 + (axis - 1); then:
 enum { ST_POT = 15, ST_ENERGY = 16, ST_OVERLAP = 17, ST_CHOL = 18, ST_TRMM = 19, ST_XY = 29,
-       ST_RHO = 30, ST_ZFIN = 31, ST_NSTAGE = 32 };
+       ST_RHO = 30, ST_ZFIN = 31, ST_CG = 32, ST_NSTAGE = 33 };
 static int stage_of(int op, int axis) {
   return op < 5 ? op * 3 + axis - 1 : 20 + (op - 5) * 3 + axis - 1;
 }
@@ -134,7 +135,7 @@ static const char* kStageNames[ST_NSTAGE] = {
     "mf_x", "mf_y", "mf_z", "mft_x", "mft_y", "mft_z", "syn_x", "syn_y", "syn_z",
     "ana_x", "ana_y", "ana_z", "kin_x", "kin_y", "kin_z", "potential", "energies",
     "overlap", "cholesky", "trmm", "cw_x", "cw_y", "cw_z", "cwt_x", "cwt_y", "cwt_z",
-    "ck_x", "ck_y", "ck_z", "xy_plane", "rho_reduce", "z_final"};
+    "ck_x", "ck_y", "ck_z", "xy_plane", "rho_reduce", "z_final", "cg_update"};
 
 namespace {
 struct Mark {
@@ -176,6 +177,22 @@ static int check_gpu(const wvl_plan* p) {
 }
 
 static inline char* wsp(void* ws, size_t off) { return (char*)ws + off; }
+
+// Preconditioner part of the workspace: three arrays of one double per
+// 256-point tile (r.z, p.p and r.r partials), eps per orbital, CG scalars.
+struct CgLayout { size_t rz, pp, rr, eps, sc, bytes; };
+static CgLayout cg_layout(const wvl_plan* p) {
+  const size_t np = align256(sizeof(double) * (size_t)p->pc[p->norb]);
+  CgLayout l;
+  l.rz = 0;
+  l.pp = np;
+  l.rr = 2 * np;
+  l.eps = 3 * np;
+  l.sc = l.eps + align256(sizeof(double) * (size_t)p->norb);
+  l.bytes = l.sc + align256(cg_scalar_bytes() * (size_t)p->norb);
+  return l;
+}
+static size_t cg_bytes(const wvl_plan* p) { return cg_layout(p).bytes; }
 
 // bytes of one packed batch array of the plan (both planes for WVL_F32C)
 static size_t batch_bytes(const wvl_plan* p) {
@@ -284,6 +301,15 @@ int wvl_plan_create(wvl_ctx* ctx, const wvl_orbital* orbs, int32_t norb, int32_t
     for (int a = 0; a < 3; ++a) {
       d.m[a] = 2 * o.n[a];
       d.kscale[a] = -1.0 / (2.0 * o.hgrid[a] * o.hgrid[a]);
+      // diagonal of A Kin S along this axis: the combined kinetic filter's
+      // taps that map a coefficient onto itself on the periodic line
+      // (offsets o = 0 mod m), for scaling (even) and wavelet (odd) outputs
+      for (int par = 0; par < 2; ++par) {
+        double sum = 0.0;
+        for (int off = WVL_CK_LO; off < WVL_CK_LO + WVL_CK_N; ++off)
+          if (off % d.m[a] == 0) sum += coef<OP_CK>(par, off, 0);
+        d.kdiag[a][par] = d.kscale[a] * sum;
+      }
     }
     d.pad = 0;
     d.off = o.off;
@@ -322,6 +348,7 @@ int wvl_plan_create(wvl_ctx* ctx, const wvl_orbital* orbs, int32_t norb, int32_t
   p->pp.assign(norb + 1, 0);
   p->pq.assign(norb + 1, 0);
   p->px2.assign(norb + 1, 0);
+  p->pc.assign(norb + 1, 0);
   for (int b = 0; b < norb; ++b) {
     const OrbDev& d = p->orbs[b];
     const int64_t m1 = d.m[0], m2 = d.m[1], m3 = d.m[2];
@@ -330,6 +357,7 @@ int wvl_plan_create(wvl_ctx* ctx, const wvl_orbital* orbs, int32_t norb, int32_t
     p->py[b + 1] = p->py[b] + (int32_t)((m1 * m3 + kThreads - 1) / kThreads);
     p->px[b + 1] = p->px[b] + (int32_t)((m2 * m3 + R - 1) / R);
     p->px2[b + 1] = p->px2[b] + (int32_t)((m2 * m3 + R2 - 1) / R2);
+    p->pc[b + 1] = p->pc[b] + (int32_t)((m1 * m2 * m3 + cg_tile_elems() - 1) / cg_tile_elems());
     p->pp[b + 1] = p->pp[b] + (int32_t)((m1 * m2 * m3 + kThreads - 1) / kThreads);
     p->pq[b + 1] = p->pq[b] + (int32_t)m3;
     if (p->pp[b + 1] < 0 || p->pz[b + 1] < 0 || p->px2[b + 1] < 0) {
@@ -407,6 +435,9 @@ int wvl_plan_create(wvl_ctx* ctx, const wvl_orbital* orbs, int32_t norb, int32_t
   p->o_A = off; off += arr;
   p->o_B = off; off += arr;
   p->o_S = off; off += arr;
+  p->o_D = off; off += arr;      // fourth batch array: preconditioner, separate-pass form
+  p->o_cg = off;                 // preconditioner: r.z, p.p, r.r tile partials, eps, scalars
+  off += cg_bytes(p);
   p->o_ez = off; off += align256(sizeof(double) * p->pz[norb]);
   p->o_ey = off; off += align256(sizeof(double) * p->py[norb]);
   p->o_ex = off; off += align256(sizeof(double) * std::max(p->px[norb], p->px2[norb]));
@@ -434,7 +465,7 @@ int wvl_plan_create(wvl_ctx* ctx, const wvl_orbital* orbs, int32_t norb, int32_t
   if (!ctx->dry) {
     hipError_t e = hipSetDevice(ctx->device);
     if (e == hipSuccess) e = hipMalloc((void**)&p->d_orbs, sizeof(OrbDev) * norb);
-    if (e == hipSuccess) e = hipMalloc((void**)&p->d_pz, sizeof(int32_t) * (norb + 1) * 17);
+    if (e == hipSuccess) e = hipMalloc((void**)&p->d_pz, sizeof(int32_t) * (norb + 1) * 18);
     if (e == hipSuccess) e = hipMalloc((void**)&p->d_info, sizeof(int) * 4);
     if (e != hipSuccess) {
       wvl_plan_destroy(p);
@@ -456,6 +487,7 @@ int wvl_plan_create(wvl_ctx* ctx, const wvl_orbital* orbs, int32_t norb, int32_t
     p->d_order_x2 = p->d_order_x + (norb + 1);
     p->d_perm_p = p->d_order_x2 + (norb + 1);
     p->d_order_p = p->d_perm_p + (norb + 1);
+    p->d_pc = p->d_order_p + (norb + 1);
     std::vector<int32_t> all;
     all.insert(all.end(), p->pz.begin(), p->pz.end());
     all.insert(all.end(), p->py.begin(), p->py.end());
@@ -463,7 +495,8 @@ int wvl_plan_create(wvl_ctx* ctx, const wvl_orbital* orbs, int32_t norb, int32_t
     all.insert(all.end(), p->pp.begin(), p->pp.end());
     all.insert(all.end(), p->pq.begin(), p->pq.end());
     for (auto* v : {&p->perm_z, &p->order_z, &p->perm_q, &p->order_q, &p->px2, &p->perm_y,
-                    &p->order_y, &p->perm_x, &p->order_x, &p->order_x2, &p->perm_p, &p->order_p}) {
+                    &p->order_y, &p->perm_x, &p->order_x, &p->order_x2, &p->perm_p, &p->order_p,
+                    &p->pc}) {
       all.insert(all.end(), v->begin(), v->end());
       all.resize(all.size() + (norb + 1 - v->size()), 0);
     }
@@ -992,6 +1025,72 @@ int wvl_energy_gradient(wvl_plan* p, const void* c, const double* V, double g_lo
     hipError_t e = launch_scale_occ(p->prec, g, p->pp[p->norb], grad, 1.0, p->elems, st);
     if (e != hipSuccess) return hipfail(e, "occupation weights");
   }
+  return WVL_OK;
+}
+
+int wvl_precondition(wvl_plan* p, const void* g, const double* eps, int32_t iters, uint32_t mode,
+                     void* gt, double* res, void* ws, void* stream) {
+  if (int r = check_plan(p)) return r;
+  if (!g || !eps || !gt || !ws) return fail(WVL_EINVAL, "wvl_precondition: NULL pointer");
+  if (iters < 0 || iters > 10000) return fail(WVL_EINVAL, "wvl_precondition: iters = %d", iters);
+  if (mode & ~(uint32_t)WVL_PRECOND_SEPARATE)
+    return fail(WVL_EINVAL, "wvl_precondition: unknown mode bits 0x%x", mode);
+  for (int b = 0; b < p->norb; ++b)
+    if (!(eps[b] < 0.0) || !isfinite(eps[b]))
+      return fail(WVL_EINVAL, "wvl_precondition: eps[%d] = %g must be negative and finite", b,
+                  eps[b]);
+  if (int r = check_disjoint(p, g, gt, "wvl_precondition")) return r;
+  if (int r = check_gpu(p)) return r;
+  hipStream_t st = (hipStream_t)stream;
+  Seq q(p, st);   // ordinary (not persistent) pass launches
+  void* R = wsp(ws, p->o_A);
+  void* Pv = wsp(ws, p->o_B);
+  void* Q = wsp(ws, p->o_S);
+  void* D = wsp(ws, p->o_D);
+  const CgLayout cl = cg_layout(p);
+  double* prz = (double*)wsp(ws, p->o_cg + cl.rz);
+  double* ppp = (double*)wsp(ws, p->o_cg + cl.pp);
+  double* prr = (double*)wsp(ws, p->o_cg + cl.rr);
+  double* eps_d = (double*)wsp(ws, p->o_cg + cl.eps);
+  void* sc = wsp(ws, p->o_cg + cl.sc);
+  double* ez = (double*)wsp(ws, p->o_ez);
+  double* ey = (double*)wsp(ws, p->o_ey);
+  double* ex = (double*)wsp(ws, p->o_ex);
+  const PassGeom gp{p->d_orbs, p->d_pc, p->norb};
+  const int nt = p->pc[p->norb];
+  const int64_t plane = p->elems;
+  const bool separate = (mode & WVL_PRECOND_SEPARATE) != 0;
+  WVL_HIP(hipMemcpyAsync(eps_d, eps, sizeof(double) * p->norb, hipMemcpyHostToDevice, st));
+  WVL_CHK(launch_cg_init(p->prec, gp, nt, g, gt, R, Pv, eps_d, plane, prz, ppp, prr, st));
+  for (int it = 0; it < iters; ++it) {
+    // q = (A Kin S - eps) p, with the kinetic energy partials p.Kin p
+    if (!separate) {
+      // combined filter (analysis o kinetic o synthesis) per axis, on the
+      // coefficients; q = Kin p here, the shift is applied in the update
+      WVL_CHK(q.pass(OP_CK, 3, Pv, Q, nullptr, 1.0, ez));
+      WVL_CHK(q.pass(OP_CK, 2, Pv, Q, Q, 1.0, ey));
+      WVL_CHK(q.pass(OP_CK, 1, Pv, Q, Q, 1.0, ex));
+    } else {
+      // the separate operations: s = S p, K = Kin s + K_0 with K_0 = -eps s
+      // (Sec. 3.4), q = A K
+      WVL_CHK(q.op3(OP_SYN, Pv, Q, D));
+      WVL_CHK(launch_cg_shift(p->prec, gp, nt, Q, D, eps_d, plane, st));
+      WVL_CHK(q.pass(OP_KIN, 3, Q, D, D, 1.0, ez));
+      WVL_CHK(q.pass(OP_KIN, 2, Q, D, D, 1.0, ey));
+      WVL_CHK(q.pass(OP_KIN, 1, Q, D, D, 1.0, ex));
+      WVL_CHK(q.op3(OP_ANA, D, Q, D));
+    }
+    {
+      Mark mk(p, st, ST_CG);
+      WVL_CHK(launch_cg_alpha(p->norb, p->d_pz, p->d_py, p->xdiv == 2 ? p->d_px2 : p->d_px, p->d_pc,
+                              ez, ey, ex, prz, ppp, eps_d, sc, st));
+      WVL_CHK(launch_cg_update1(p->prec, gp, nt, gt, R, Pv, Q, eps_d, separate ? 0 : 1, sc, plane,
+                                prz, prr, st));
+      WVL_CHK(launch_cg_beta(p->norb, p->d_pc, prz, sc, st));
+      WVL_CHK(launch_cg_update2(p->prec, gp, nt, R, Pv, eps_d, sc, plane, ppp, st));
+    }
+  }
+  if (res) WVL_CHK(launch_cg_res(p->norb, p->d_pc, prr, res, st));
   return WVL_OK;
 }
 

@@ -104,6 +104,8 @@ struct OrbDev {
   int64_t voff;        // element offset of its potential (0 for a shared V)
   double kscale[3];    // -1 / (2 h_a^2), per axis
   double occ;          // occupation f_i
+  double kdiag[3][2];  // diagonal of the kinetic operator in the wavelet basis,
+                       // per axis: [0] scaling, [1] wavelet coefficients
 };
 
 // Tiling of one kind of pass: tile t of the launch belongs to the orbital b

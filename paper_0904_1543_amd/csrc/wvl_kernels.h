@@ -55,6 +55,32 @@ hipError_t launch_pot_orb(int prec, const PassGeom& g, int ntiles, const void* p
 hipError_t launch_scale_occ(int prec, const PassGeom& g, int ntiles, void* x, double mul,
                             int64_t plane, hipStream_t st);
 
+// Preconditioner: vector stages of the conjugate-gradient iteration (see
+// wvl_precond.hip).  g: tiles of cg_tile_elems() points (prefix pc); sc:
+// per-orbital scalars (cg_scalar_bytes() each); partial arrays: one double
+// per tile.
+size_t cg_scalar_bytes();
+int cg_tile_elems();
+hipError_t launch_cg_init(int prec, const PassGeom& g, int ntiles, const void* gin, void* x,
+                          void* r, void* p, const double* eps, int64_t plane, double* prz,
+                          double* ppp, double* prr, hipStream_t st);
+hipError_t launch_cg_alpha(int norb, const int32_t* pz, const int32_t* py, const int32_t* px,
+                           const int32_t* pp, const double* ez, const double* ey, const double* ex,
+                           const double* prz, const double* ppp, const double* eps, void* sc,
+                           hipStream_t st);
+hipError_t launch_cg_update1(int prec, const PassGeom& g, int ntiles, void* x, void* r,
+                             const void* p, const void* q, const double* eps, int shift,
+                             const void* sc, int64_t plane, double* prz, double* prr,
+                             hipStream_t st);
+hipError_t launch_cg_beta(int norb, const int32_t* pp, const double* prz, void* sc, hipStream_t st);
+hipError_t launch_cg_update2(int prec, const PassGeom& g, int ntiles, const void* r, void* p,
+                             const double* eps, const void* sc, int64_t plane, double* ppp,
+                             hipStream_t st);
+hipError_t launch_cg_shift(int prec, const PassGeom& g, int ntiles, const void* s, void* k0,
+                           const double* eps, int64_t plane, hipStream_t st);
+hipError_t launch_cg_res(int norb, const int32_t* pp, const double* prr, double* res,
+                         hipStream_t st);
+
 // Per-orbital energies eorb[b] (potential) and eorb[norb + b] (kinetic) from
 // the tile partials; pot_mode 0: none, 1: per-orbital tiles (prefix pp),
 // 2: shared-grid blocks laid out [norb][nblk].

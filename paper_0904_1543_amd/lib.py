@@ -22,6 +22,7 @@ WVL_F64, WVL_F32, WVL_F32C = 0, 1, 2
 WVL_SHARED_V, WVL_USE_GRAPH, WVL_PERSISTENT, WVL_AUTOTUNE = 1, 2, 4, 8
 (WVL_Q_VARIANT, WVL_Q_GROUP, WVL_Q_PERSISTENT, WVL_Q_XDIV, WVL_Q_PGRID, WVL_Q_TUNE_BEST,
  WVL_Q_FUSED_Z) = range(7)
+WVL_PRECOND_SEPARATE = 1
 
 STATUS_NAMES = {0: "WVL_OK", -1: "WVL_EINVAL", -2: "WVL_EUNSUPPORTED", -3: "WVL_ENOMEM",
                 -4: "WVL_EHIP", -5: "WVL_ETIMEOUT", -6: "WVL_ENODEV"}
@@ -73,6 +74,7 @@ _SIGS = {
     "wvl_plan_tuning": [P, ctypes.POINTER(I32), DP, I32],
     "wvl_plan_query": [P, I32, ctypes.POINTER(I64)],
     "wvl_energy_gradient": [P, P, P, D, D, P, P, P],
+    "wvl_precondition": [P, P, DP, I32, ctypes.c_uint32, P, P, P, P],
     "wvl_plan_profile": [P, I32],
     "wvl_plan_profile_read": [P, ctypes.POINTER(I32), DP, I32, ctypes.POINTER(I32)],
 }

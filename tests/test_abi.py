@@ -205,3 +205,19 @@ def test_noalloc_orthonormalize_checks(dry):
     assert f(None, a, None, None, None) == lib.WVL_EINVAL
     assert f(p, a, None, None, None) == lib.WVL_ENODEV             # valid, but no GPU
     lib.wvl_plan_destroy(p)
+
+
+def test_precondition_checks(dry):
+    rc, p = _plan(dry, [(4, 4, 4)] * 2)
+    f = lib.raw("wvl_precondition")
+    a, b, ws = ctypes.c_void_p(0x100000), ctypes.c_void_p(0x200000), ctypes.c_void_p(0x300000)
+    good = (ctypes.c_double * 2)(-0.5, -0.2)
+    bad = (ctypes.c_double * 2)(-0.5, 0.0)
+    assert f(p, a, good, 3, 0, b, None, ws, None) == lib.WVL_ENODEV
+    assert f(p, a, bad, 3, 0, b, None, ws, None) == lib.WVL_EINVAL       # eps must be < 0
+    assert "eps[1]" in lib.wvl_last_error()
+    assert f(p, a, good, -1, 0, b, None, ws, None) == lib.WVL_EINVAL     # iters
+    assert f(p, a, good, 3, 4, b, None, ws, None) == lib.WVL_EINVAL      # unknown mode
+    assert f(p, a, None, 3, 0, b, None, ws, None) == lib.WVL_EINVAL
+    assert f(p, a, good, 3, 0, a, None, ws, None) == lib.WVL_EINVAL      # gt overlaps g
+    lib.wvl_plan_destroy(p)

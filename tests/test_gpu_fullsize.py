@@ -91,3 +91,20 @@ def test_density_and_e_loc_full_batch(c3, c3_density, prec):
     assert_scalar(r["energies"][0].item(), eloc_ref, tol, "E_loc")
     del r
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32c"])
+def test_precondition_full_batch_sampled(c3, prec):
+    """The preconditioner on the 256 x 96^3 batch: sampled orbitals against
+    the oracle running the same 3 conjugate-gradient steps."""
+    from oracle import precond as PC
+    eps = -inputs.rng_for(31).uniform(0.1, 1.0, size=len(c3["dims"]))
+    plan = ops.Plan(c3["dims"], prec=prec)
+    gt = plan.to_f64(plan.precondition(plan.pack(c3["C"]), eps, 3))
+    M = plan.M[0]
+    tol = TOL[prec]
+    for b in (0, 200):
+        ref, _ = PC.pcg(c3["C"][b], eps[b], 3)
+        assert_close(gt[b * M:(b + 1) * M].cpu().numpy(), ref, tol, f"orbital {b}")
+    del gt
+    torch.cuda.empty_cache()
