@@ -156,6 +156,41 @@ def random_uneven_case(seed, norb, lo=4, hi=12):
                 hgrid=(1.0, 1.0, 1.0), shared_v=False)
 
 
+def sphere_regions(seed, dims, natoms=4, rc=0.3, rf=0.15):
+    """Synthetic coarse and fine regions of a periodic box of coarse dims
+    (n1, n2, n3), shaped like those of an atomic system: `natoms` centres
+    uniform in the box; the coarse region is every coarse point within
+    rc * min(dims) of a centre, the fine region within rf * min(dims)
+    (periodic minimum-image distances, in coarse spacings).  Returned as
+    segment lists [start, end) of consecutive points along axis 1 in the
+    linear coarse index i1 + n1 (i2 + n2 i3), int32 arrays of shape (k, 2)."""
+    n1, n2, n3 = dims
+    rng = rng_for(seed)
+    centres = rng.uniform(0.0, 1.0, size=(natoms, 3)) * np.array([n1, n2, n3])
+    i3, i2, i1 = np.meshgrid(np.arange(n3), np.arange(n2), np.arange(n1), indexing="ij")
+    d2 = np.full((n3, n2, n1), np.inf)
+    for c1, c2, c3 in centres:
+        e = [(np.asarray(i, dtype=np.float64) - c + n / 2.0) % n - n / 2.0
+             for i, c, n in ((i1, c1, n1), (i2, c2, n2), (i3, c3, n3))]
+        d2 = np.minimum(d2, e[0] ** 2 + e[1] ** 2 + e[2] ** 2)
+    lim = float(min(dims))
+    return (segments_of_mask(d2 <= (rc * lim) ** 2), segments_of_mask(d2 <= (rf * lim) ** 2))
+
+
+def segments_of_mask(mask):
+    """[start, end) runs of True along the last axis of a (n3, n2, n1) mask,
+    in linear index order."""
+    flat = np.asarray(mask, dtype=bool)
+    n1 = flat.shape[-1]
+    rows = flat.reshape(-1, n1)
+    segs = []
+    for r, row in enumerate(rows):
+        d = np.diff(np.concatenate([[0], row.astype(np.int8), [0]]))
+        for a, b in zip(np.flatnonzero(d == 1), np.flatnonzero(d == -1)):
+            segs.append((r * n1 + a, r * n1 + b))
+    return np.asarray(segs, dtype=np.int32).reshape(-1, 2)
+
+
 def directions(seed, shape, count):
     """``count`` unit-norm N(0,1) directions of the given shape."""
     rng = rng_for(seed)
