@@ -297,6 +297,58 @@ def run_precond(C, dims, steps, warmup, check):
     return out
 
 
+def run_compressed(C, V, dims, steps, warmup, check):
+    """Local H*psi on compressed orbitals (steps 1-7 of Sec. 2.4) on the same
+    batch, float64: coarse and fine regions of 4 atom-like spheres (radius
+    0.3 and 0.15 of the box, periodic), the coefficients outside the regions
+    dropped."""
+    import torch
+    from paper_0904_1543_amd import inputs, ops
+
+    norb = len(dims)
+    d0 = dims[0]
+    seg_c, seg_f = inputs.sphere_regions(33, d0, natoms=4, rc=0.3, rf=0.15)
+    plan = ops.Plan(dims, prec="f64")
+    nvc, nvf = plan.set_regions(seg_c, seg_f)
+    psi_c = plan.compress(plan.pack(C))
+    Vt = plan.pack_potential(V)
+    out = plan.empty_compressed()
+
+    def call():
+        plan.local_hpsi_compressed(psi_c, Vt, out=out, rho=False, energies=False)
+
+    for _ in range(max(1, warmup)):
+        call()
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(steps):
+        call()
+    t1.record()
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / steps
+    pts = norb * int(np.prod(inputs.fine_shape(d0)))
+    res = {"workload": f"{norb} orbitals, coarse {d0[0]}^3, 4 spherical coarse/fine regions "
+                       "(radius 0.3 / 0.15 of the box), float64",
+           "nvctr_c": nvc, "nvctr_f": nvf, "compressed_fraction": (nvc + 7 * nvf) / (pts / norb),
+           "ms_per_hpsi": ms, "orbital_gridpoints_per_s": pts / (ms * 1e-3)}
+    if check:
+        from oracle import compress as CP
+        got = plan.unpack_compressed(out)
+        num = den = 0.0
+        for b in (0, norb - 1):
+            v = CP.compress(C[b], seg_c, seg_f, d0)
+            ref, _ = CP.local_hpsi_compressed(v, V, seg_c, seg_f, d0)
+            num += float(np.sum((got[b] - ref) ** 2))
+            den += float(np.sum(ref ** 2))
+        res["rel_err_vs_oracle"] = {"orbitals": [0, norb - 1], "normwise": (num / den) ** 0.5,
+                                    "tolerance": TOL["f64"]}
+    del plan, psi_c, Vt, out
+    torch.cuda.empty_cache()
+    return res
+
+
 def run_uneven(steps, warmup):
     """The 512-orbital uneven batch, compensated float32, persistent launches
     in a replayed hipGraph, launch sequence chosen by the tuner."""
@@ -413,6 +465,9 @@ def main():
                                       not args.no_cpu_baseline)
         torch.cuda.empty_cache()
 
+    print("[bench] compressed orbitals", file=sys.stderr, flush=True)
+    compressed = run_compressed(C, V, dims, args.steps, 2, not args.no_cpu_baseline)
+
     print("[bench] preconditioner", file=sys.stderr, flush=True)
     precond = run_precond(C, dims, max(3, args.steps // 4), 1, not args.no_cpu_baseline)
 
@@ -510,6 +565,7 @@ def main():
             for p, v in results.items()},
         "uneven_batch": uneven,
         "preconditioner": precond,
+        "compressed_hpsi": compressed,
     }
     print(json.dumps(line))
 

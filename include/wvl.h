@@ -153,6 +153,39 @@ int wvl_local_hpsi(wvl_plan *plan, const void *c, const double *V, double pot_sc
                    double kin_scale, void *hpsi, double *rho, double *e_loc, double *e_kin,
                    double *e_orb, void *ws, void *stream);
 
+/* Compressed storage (Sec. 2.1): an orbital keeps its scaling coefficient
+ * only at the coarse grid points of the low-resolution region and its seven
+ * wavelet coefficients only at the points of the high-resolution region.
+ * wvl_plan_set_regions() fixes the two regions of a plan whose orbitals all
+ * share one grid.  A region is `nseg` segments [start, end) (int32 pairs,
+ * HOST memory) of consecutive coarse points in the linear coarse index
+ * i1 + n1 (i2 + n2 i3), increasing and disjoint, inside [0, n1 n2 n3); the
+ * fine region need not lie inside the coarse one.  The call allocates and
+ * uploads per-point maps (2 n1 n2 n3 int32) and the region point lists;
+ * calling it again replaces them.
+ * Compressed vector of one orbital: the nvctr_c coarse-region scaling
+ * coefficients in segment order, then for every one of the nvctr_f
+ * fine-region points in segment order its components mu = 1..7 (mu = b1 +
+ * 2 b2 + 4 b3: wavelet along the axes whose bit is set), L = nvctr_c +
+ * 7 nvctr_f values.  A compressed batch array holds orbital b at b * L, in
+ * the plan precision (WVL_F32C: hi plane then lo plane of norb * L floats). */
+int wvl_plan_set_regions(wvl_plan *plan, const int32_t *seg_c, int32_t nseg_c,
+                         const int32_t *seg_f, int32_t nseg_f);
+int wvl_plan_compressed_size(const wvl_plan *plan, int64_t *nvctr_c, int64_t *nvctr_f);
+/* Step 1 of Sec. 2.4: the full coefficient array c (a batch array of the plan,
+ * zero outside the regions) from the compressed batch psi_c. */
+int wvl_decompress(wvl_plan *plan, const void *psi_c, void *c, void *stream);
+/* Step 7 of Sec. 2.4: the region coefficients of c, packed into psi_c. */
+int wvl_compress(wvl_plan *plan, const void *c, void *psi_c, void *stream);
+/* Local Hamiltonian on compressed orbitals, steps 1-7 of Sec. 2.4:
+ * decompress into the workspace, wvl_local_hpsi on the whole grid (in place
+ * there), compress into hpsi_c, which may be psi_c itself.  The other
+ * arguments and outputs are those of wvl_local_hpsi (rho and the energies of
+ * the decompressed orbitals).  WVL_EUNSUPPORTED without regions. */
+int wvl_local_hpsi_compressed(wvl_plan *plan, const void *psi_c, const double *V,
+                              double pot_scale, double kin_scale, void *hpsi_c, double *rho,
+                              double *e_loc, double *e_kin, double *e_orb, void *ws, void *stream);
+
 /* Gradient of the energy functional E = g_loc E_loc + g_kin E_kin with respect
  * to the coefficients (Sec. 2 and Sec. 5: the minimisation needs the gradient
  * of the total energy with respect to every orbital).  Both energies are

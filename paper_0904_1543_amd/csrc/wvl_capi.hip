@@ -106,6 +106,9 @@ struct wvl_plan {
   int32_t *d_px2 = nullptr, *d_perm_y = nullptr, *d_order_y = nullptr, *d_perm_x = nullptr,
           *d_order_x = nullptr, *d_order_x2 = nullptr, *d_perm_p = nullptr, *d_order_p = nullptr;
   int* d_info = nullptr;
+  // compressed storage (Sec. 2.1): regions of a uniform batch
+  int64_t nvc = -1, nvf = 0;   // coarse-region and fine-region points (-1: no regions)
+  int32_t *d_map_c = nullptr, *d_map_f = nullptr, *d_list_c = nullptr, *d_list_f = nullptr;
   // workspace layout (byte offsets)
   size_t ws = 0, o_A = 0, o_B = 0, o_S = 0, o_D = 0, o_cg = 0, o_ez = 0, o_ey = 0, o_ex = 0, o_pp = 0, o_rv = 0,
          o_rho = 0, o_eorb = 0, o_syrk = 0, o_L = 0, o_Li = 0, o_T = 0, o_rhop = 0, o_epl = 0,
@@ -532,6 +535,7 @@ int wvl_plan_destroy(wvl_plan* p) {
     if (p->d_orbs) (void)hipFree(p->d_orbs);
     if (p->d_pz) (void)hipFree(p->d_pz);
     if (p->d_info) (void)hipFree(p->d_info);
+    if (p->d_map_c) (void)hipFree(p->d_map_c);
   }
   delete p;
   return WVL_OK;
@@ -1091,6 +1095,132 @@ int wvl_precondition(wvl_plan* p, const void* g, const double* eps, int32_t iter
     }
   }
   if (res) WVL_CHK(launch_cg_res(p->norb, p->d_pc, prr, res, st));
+  return WVL_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Compressed storage (Sec. 2.1; steps 1 and 7 of Sec. 2.4)
+// ---------------------------------------------------------------------------
+static int check_segments(const int32_t* seg, int32_t nseg, int64_t npts, const char* what,
+                          int64_t* count) {
+  if (nseg < 0) return fail(WVL_EINVAL, "%s: negative segment count", what);
+  if (nseg > 0 && !seg) return fail(WVL_EINVAL, "%s: NULL segments", what);
+  int64_t prev = 0, n = 0;
+  for (int32_t k = 0; k < nseg; ++k) {
+    const int64_t a = seg[2 * k], b = seg[2 * k + 1];
+    if (a < prev || b <= a || b > npts)
+      return fail(WVL_EINVAL, "%s: segment %d [%lld, %lld) out of order or outside [0, %lld)", what,
+                  k, (long long)a, (long long)b, (long long)npts);
+    n += b - a;
+    prev = b;
+  }
+  *count = n;
+  return WVL_OK;
+}
+
+int wvl_plan_set_regions(wvl_plan* p, const int32_t* seg_c, int32_t nseg_c, const int32_t* seg_f,
+                         int32_t nseg_f) {
+  if (int r = check_plan(p)) return r;
+  if (p->M == 0) return fail(WVL_EUNSUPPORTED, "regions need every orbital on the same grid");
+  const int64_t npts = p->M / 8;
+  int64_t nvc = 0, nvf = 0;
+  if (int r = check_segments(seg_c, nseg_c, npts, "coarse region", &nvc)) return r;
+  if (int r = check_segments(seg_f, nseg_f, npts, "fine region", &nvf)) return r;
+  if (nvc + 7 * nvf > ((int64_t)1 << 31) - 1) return fail(WVL_EINVAL, "regions too large");
+  if (int r = check_gpu(p)) return r;
+  std::vector<int32_t> host((size_t)(2 * npts + nvc + nvf), -1);
+  int32_t* map_c = host.data();
+  int32_t* map_f = map_c + npts;
+  int32_t* list_c = map_f + npts;
+  int32_t* list_f = list_c + nvc;
+  int64_t k = 0;
+  for (int32_t s = 0; s < nseg_c; ++s)
+    for (int32_t q = seg_c[2 * s]; q < seg_c[2 * s + 1]; ++q) { map_c[q] = (int32_t)k; list_c[k++] = q; }
+  k = 0;
+  for (int32_t s = 0; s < nseg_f; ++s)
+    for (int32_t q = seg_f[2 * s]; q < seg_f[2 * s + 1]; ++q) { map_f[q] = (int32_t)k; list_f[k++] = q; }
+  if (p->d_map_c) { WVL_HIP(hipFree(p->d_map_c)); p->d_map_c = nullptr; }
+  void* d = nullptr;
+  hipError_t e = hipMalloc(&d, sizeof(int32_t) * host.size());
+  if (e != hipSuccess) return fail(WVL_ENOMEM, "region maps: %s", hipGetErrorString(e));
+  e = hipMemcpy(d, host.data(), sizeof(int32_t) * host.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) { (void)hipFree(d); return hipfail(e, "region upload"); }
+  p->d_map_c = (int32_t*)d;
+  p->d_map_f = p->d_map_c + npts;
+  p->d_list_c = p->d_map_f + npts;
+  p->d_list_f = p->d_list_c + nvc;
+  p->nvc = nvc;
+  p->nvf = nvf;
+  return WVL_OK;
+}
+
+int wvl_plan_compressed_size(const wvl_plan* p, int64_t* nvctr_c, int64_t* nvctr_f) {
+  if (int r = check_plan(p)) return r;
+  if (!nvctr_c || !nvctr_f) return fail(WVL_EINVAL, "NULL output");
+  if (p->nvc < 0) return fail(WVL_EUNSUPPORTED, "no regions set (wvl_plan_set_regions)");
+  *nvctr_c = p->nvc;
+  *nvctr_f = p->nvf;
+  return WVL_OK;
+}
+
+static int check_compressed(const wvl_plan* p, const char* what) {
+  if (p->nvc < 0) return fail(WVL_EUNSUPPORTED, "%s: no regions set (wvl_plan_set_regions)", what);
+  return WVL_OK;
+}
+
+// bytes of one compressed batch array (both planes for WVL_F32C)
+static size_t cbatch_bytes(const wvl_plan* p) {
+  return (size_t)((p->nvc + 7 * p->nvf) * p->norb) * (p->prec == WVL_F32 ? 4 : 8);
+}
+
+int wvl_decompress(wvl_plan* p, const void* psi_c, void* c, void* stream) {
+  if (int r = check_plan(p)) return r;
+  if (!psi_c || !c) return fail(WVL_EINVAL, "wvl_decompress: NULL pointer");
+  if (int r = check_compressed(p, "wvl_decompress")) return r;
+  if (overlap(psi_c, cbatch_bytes(p), c, batch_bytes(p)))
+    return fail(WVL_EINVAL, "wvl_decompress: output overlaps input");
+  if (int r = check_gpu(p)) return r;
+  const int64_t L = p->nvc + 7 * p->nvf;
+  WVL_CHK(launch_decompress(p->prec, p->d_orbs, p->norb, p->M, p->d_map_c, p->d_map_f, p->nvc, L,
+                            psi_c, L * p->norb, c, p->elems, (hipStream_t)stream));
+  return WVL_OK;
+}
+
+int wvl_compress(wvl_plan* p, const void* c, void* psi_c, void* stream) {
+  if (int r = check_plan(p)) return r;
+  if (!psi_c || !c) return fail(WVL_EINVAL, "wvl_compress: NULL pointer");
+  if (int r = check_compressed(p, "wvl_compress")) return r;
+  if (overlap(psi_c, cbatch_bytes(p), c, batch_bytes(p)))
+    return fail(WVL_EINVAL, "wvl_compress: output overlaps input");
+  if (int r = check_gpu(p)) return r;
+  const int64_t L = p->nvc + 7 * p->nvf;
+  WVL_CHK(launch_compress(p->prec, p->d_orbs, p->norb, p->d_list_c, p->d_list_f, p->nvc, L, c,
+                          p->elems, psi_c, L * p->norb, (hipStream_t)stream));
+  return WVL_OK;
+}
+
+int wvl_local_hpsi_compressed(wvl_plan* p, const void* psi_c, const double* V, double pot_scale,
+                              double kin_scale, void* hpsi_c, double* rho, double* e_loc,
+                              double* e_kin, double* e_orb, void* ws, void* stream) {
+  if (int r = check_plan(p)) return r;
+  if (!psi_c || !V || !hpsi_c || !ws) return fail(WVL_EINVAL, "wvl_local_hpsi_compressed: NULL pointer");
+  if (int r = check_compressed(p, "wvl_local_hpsi_compressed")) return r;
+  if (rho && !p->shared) return fail(WVL_EUNSUPPORTED, "rho needs a WVL_SHARED_V plan");
+  if (!isfinite(pot_scale) || !isfinite(kin_scale))
+    return fail(WVL_EINVAL, "wvl_local_hpsi_compressed: scales must be finite");
+  if (hpsi_c != psi_c && overlap(psi_c, cbatch_bytes(p), hpsi_c, cbatch_bytes(p)))
+    return fail(WVL_EINVAL, "wvl_local_hpsi_compressed: hpsi_c overlaps psi_c without being it");
+  if (int r = check_gpu(p)) return r;
+  hipStream_t st = (hipStream_t)stream;
+  const int64_t L = p->nvc + 7 * p->nvf;
+  void* full = wsp(ws, p->o_D);
+  // step 1: unpack onto the whole grid; steps 2-6 in place; step 7: pack
+  WVL_CHK(launch_decompress(p->prec, p->d_orbs, p->norb, p->M, p->d_map_c, p->d_map_f, p->nvc, L,
+                            psi_c, L * p->norb, full, p->elems, st));
+  if (int r = hpsi_sequence(p, st, full, V, pot_scale, kin_scale, full, rho, e_loc, e_kin, e_orb, ws))
+    return r;
+  WVL_CHK(launch_compress(p->prec, p->d_orbs, p->norb, p->d_list_c, p->d_list_f, p->nvc, L, full,
+                          p->elems, hpsi_c, L * p->norb, st));
   return WVL_OK;
 }
 

@@ -81,6 +81,16 @@ hipError_t launch_cg_shift(int prec, const PassGeom& g, int ntiles, const void* 
 hipError_t launch_cg_res(int norb, const int32_t* pp, const double* prr, double* res,
                          hipStream_t st);
 
+// Compressed storage (wvl_compress.hip): uniform batch of norb orbitals of M
+// points; compressed vectors of L = nvc + 7 nvf values at b * L.
+hipError_t launch_decompress(int prec, const OrbDev* orbs, int norb, int64_t M,
+                             const int32_t* map_c, const int32_t* map_f, int64_t nvc, int64_t L,
+                             const void* in, int64_t plane_in, void* out, int64_t plane_out,
+                             hipStream_t st);
+hipError_t launch_compress(int prec, const OrbDev* orbs, int norb, const int32_t* list_c,
+                           const int32_t* list_f, int64_t nvc, int64_t L, const void* in,
+                           int64_t plane_in, void* out, int64_t plane_out, hipStream_t st);
+
 // Per-orbital energies eorb[b] (potential) and eorb[norb + b] (kinetic) from
 // the tile partials; pot_mode 0: none, 1: per-orbital tiles (prefix pp),
 // 2: shared-grid blocks laid out [norb][nblk].

@@ -75,6 +75,11 @@ _SIGS = {
     "wvl_plan_query": [P, I32, ctypes.POINTER(I64)],
     "wvl_energy_gradient": [P, P, P, D, D, P, P, P],
     "wvl_precondition": [P, P, DP, I32, ctypes.c_uint32, P, P, P, P],
+    "wvl_plan_set_regions": [P, ctypes.POINTER(I32), I32, ctypes.POINTER(I32), I32],
+    "wvl_plan_compressed_size": [P, ctypes.POINTER(I64), ctypes.POINTER(I64)],
+    "wvl_decompress": [P, P, P, P],
+    "wvl_compress": [P, P, P, P],
+    "wvl_local_hpsi_compressed": [P, P, P, D, D, P, P, P, P, P, P, P],
     "wvl_plan_profile": [P, I32],
     "wvl_plan_profile_read": [P, ctypes.POINTER(I32), DP, I32, ctypes.POINTER(I32)],
 }

@@ -215,6 +215,65 @@ class Plan:
                              ptr(self.ws), stream_handle())
         return (out, res) if residuals else out
 
+    # ------------------------------------------------------------ compressed form
+    def set_regions(self, seg_c, seg_f):
+        """Coarse and fine regions as (k, 2) int32 segment arrays [start, end)."""
+        sc = np.ascontiguousarray(np.asarray(seg_c, dtype=np.int32).reshape(-1, 2))
+        sf = np.ascontiguousarray(np.asarray(seg_f, dtype=np.int32).reshape(-1, 2))
+        I32P = ctypes.POINTER(ctypes.c_int32)
+        lib.wvl_plan_set_regions(self.h, sc.ctypes.data_as(I32P), len(sc),
+                                 sf.ctypes.data_as(I32P), len(sf))
+        a, b = ctypes.c_int64(), ctypes.c_int64()
+        lib.wvl_plan_compressed_size(self.h, ctypes.byref(a), ctypes.byref(b))
+        self.nvctr = (a.value, b.value)
+        self.clen = a.value + 7 * b.value
+        return self.nvctr
+
+    def empty_compressed(self):
+        n = self.clen * self.norb
+        if self.prec == "f64":
+            return torch.empty(n, dtype=torch.float64, device=self.dev)
+        if self.prec == "f32":
+            return torch.empty(n, dtype=torch.float32, device=self.dev)
+        return torch.empty((2, n), dtype=torch.float32, device=self.dev)
+
+    def pack_compressed(self, vectors):
+        """float64 host vectors (one per orbital) -> compressed batch tensor."""
+        t64 = torch.from_numpy(np.concatenate([np.asarray(v, dtype=np.float64).ravel()
+                                               for v in vectors])).to(self.dev)
+        if self.prec == "f64":
+            return t64
+        return self.convert(t64, "f64", self.prec, self.clen * self.norb)
+
+    def unpack_compressed(self, t):
+        flat = (t if self.prec == "f64" else
+                self.convert(t, self.prec, "f64", self.clen * self.norb)).cpu().numpy()
+        return [flat[b * self.clen:(b + 1) * self.clen] for b in range(self.norb)]
+
+    def decompress(self, psi_c, out=None):
+        out = self.empty() if out is None else out
+        lib.wvl_decompress(self.h, ptr(psi_c), ptr(out), stream_handle())
+        return out
+
+    def compress(self, c, out=None):
+        out = self.empty_compressed() if out is None else out
+        lib.wvl_compress(self.h, ptr(c), ptr(out), stream_handle())
+        return out
+
+    def local_hpsi_compressed(self, psi_c, V, pot_scale=1.0, kin_scale=1.0, out=None, rho=True,
+                              energies=True, per_orbital=False):
+        out = self.empty_compressed() if out is None else out
+        r = torch.empty(self.M[0], dtype=torch.float64, device=self.dev) \
+            if (rho and self.shared_v) else None
+        e = torch.empty(2, dtype=torch.float64, device=self.dev) if energies else None
+        eo = torch.empty(2 * self.norb, dtype=torch.float64, device=self.dev) if per_orbital else None
+        e_loc = ctypes.c_void_p(e.data_ptr()) if e is not None else None
+        e_kin = ctypes.c_void_p(e.data_ptr() + 8) if e is not None else None
+        lib.wvl_local_hpsi_compressed(self.h, ptr(psi_c), ptr(V), float(pot_scale), float(kin_scale),
+                                      ptr(out), ptr(r), e_loc, e_kin, ptr(eo), ptr(self.ws),
+                                      stream_handle())
+        return dict(hpsi=out, rho=r, energies=e, e_orb=eo)
+
     def query(self, what):
         """A plan property (lib.WVL_Q_*)."""
         v = ctypes.c_int64()

@@ -221,3 +221,29 @@ def test_precondition_checks(dry):
     assert f(p, a, None, 3, 0, b, None, ws, None) == lib.WVL_EINVAL
     assert f(p, a, good, 3, 0, a, None, ws, None) == lib.WVL_EINVAL      # gt overlaps g
     lib.wvl_plan_destroy(p)
+
+
+def test_region_checks(dry):
+    rc, p = _plan(dry, [(4, 4, 4)] * 2)          # 64 coarse points
+    f = lib.raw("wvl_plan_set_regions")
+    I32 = ctypes.c_int32
+
+    def segs(*pairs):
+        flat = [v for pq in pairs for v in pq]
+        return (I32 * max(1, len(flat)))(*flat), len(pairs)
+
+    good, n = segs((0, 5), (8, 20))
+    assert f(p, good, n, good, n) == lib.WVL_ENODEV                     # valid: no GPU
+    for bad in (segs((5, 5)), segs((0, 65)), segs((8, 20), (0, 5)), segs((0, 10), (9, 12)),
+                segs((-1, 3))):
+        assert f(p, bad[0], bad[1], good, n) == lib.WVL_EINVAL
+    assert f(p, None, 1, good, n) == lib.WVL_EINVAL
+    a, b = ctypes.c_int64(), ctypes.c_int64()
+    assert lib.raw("wvl_plan_compressed_size")(p, ctypes.byref(a), ctypes.byref(b)) == \
+        lib.WVL_EUNSUPPORTED                                             # no regions yet
+    x, y = ctypes.c_void_p(0x100000), ctypes.c_void_p(0x200000)
+    assert lib.raw("wvl_decompress")(p, x, y, None) == lib.WVL_EUNSUPPORTED
+    lib.wvl_plan_destroy(p)
+    rc, p = _plan(dry, [(4, 4, 4), (4, 6, 4)], flags=0)                 # uneven batch
+    assert f(p, good, n, good, n) == lib.WVL_EUNSUPPORTED
+    lib.wvl_plan_destroy(p)
