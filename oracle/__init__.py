@@ -9,4 +9,4 @@ mathematics (closed forms, invariants, brute-force dense matrices, Fourier
 identities, exact finite differences); none is "parity unpinned".
 """
 
-from . import compress, filters, precond, wavelet  # noqa: F401
+from . import boundary, compress, filters, precond, wavelet  # noqa: F401
