@@ -18,6 +18,8 @@ Readings (the paper gives the equation and the method's name, nothing more):
   * the CG preconditioner is the diagonal of H_eps in the wavelet basis
     (Jacobi); the kinetic part of the diagonal depends only on whether a
     coefficient is a scaling or a wavelet coefficient along each axis;
+  * with isolated or surface boundary conditions the same, with the
+    operators of those conditions;
   * the iteration starts from g~ = 0 and runs a fixed number of steps; a step
     whose curvature p.H p or previous r.z is not positive leaves the iterate
     unchanged (alpha = 0, beta = 0), which only happens for g = 0.
@@ -25,40 +27,49 @@ Readings (the paper gives the equation and the method's name, nothing more):
 
 import numpy as np
 
+from . import boundary as BC
 from . import wavelet as W
 
 
-def helmholtz(c, eps, hgrid=(1.0, 1.0, 1.0)):
-    """H_eps c = A (Kin (S c) + K_0) with K_0 = -eps S c (Sec. 3.4)."""
-    s = W.synthesis(c)
-    return W.analysis(W.kinetic(s, hgrid, k0=-eps * s))
+def helmholtz(c, eps, hgrid=(1.0, 1.0, 1.0), bc="periodic"):
+    """H_eps c = A (Kin (S c) + K_0) with K_0 = -eps S c (Sec. 3.4), with the
+    boundary condition `bc` ("periodic", "free", "surface")."""
+    if bc == "periodic":
+        s = W.synthesis(c)
+        return W.analysis(W.kinetic(s, hgrid, k0=-eps * s))
+    s = BC.synthesis(c, bc)
+    return BC.analysis(BC.kinetic(s, bc, hgrid, k0=-eps * s), bc)
 
 
-def kinetic_diagonal_1d(m, hgrid):
-    """Diagonal of the 1D operator A Kin S on a periodic line of m
-    coefficients, one column at a time (unit vectors through the 1D
-    synthesis, kinetic filter and analysis)."""
+def kinetic_diagonal_1d(m, hgrid, free=False):
+    """Diagonal of the 1D operator A Kin S on a line of m coefficients
+    (periodic, or isolated), one column at a time (unit vectors through the
+    1D synthesis, kinetic filter and analysis)."""
     d = np.empty(m)
     for j in range(m):
         e = np.zeros(m)
         e[j] = 1.0
-        col = W.analysis_1d(W.kinetic_1d(W.synthesis_1d(e, -1), -1, hgrid), -1)
+        if free:
+            col = BC.analysis_1d_free(BC.kinetic_1d_free(BC.synthesis_1d_free(e, -1), -1, hgrid), -1)
+        else:
+            col = W.analysis_1d(W.kinetic_1d(W.synthesis_1d(e, -1), -1, hgrid), -1)
         d[j] = col[j]
     return d
 
 
-def helmholtz_diagonal(shape, eps, hgrid=(1.0, 1.0, 1.0)):
+def helmholtz_diagonal(shape, eps, hgrid=(1.0, 1.0, 1.0), bc="periodic"):
     """Diagonal of H_eps on a (m3, m2, m1) grid: A Kin S is the sum over axes
     of the 1D operator along that axis (A_a S_a = I on the others), so its
     diagonal is d_1[i1] + d_2[i2] + d_3[i3]; then minus eps."""
     m3, m2, m1 = shape
-    d1 = kinetic_diagonal_1d(m1, hgrid[0])
-    d2 = kinetic_diagonal_1d(m2, hgrid[1])
-    d3 = kinetic_diagonal_1d(m3, hgrid[2])
+    free = BC.BCS[bc]
+    d1 = kinetic_diagonal_1d(m1, hgrid[0], free[0] == "f")
+    d2 = kinetic_diagonal_1d(m2, hgrid[1], free[1] == "f")
+    d3 = kinetic_diagonal_1d(m3, hgrid[2], free[2] == "f")
     return d3[:, None, None] + d2[None, :, None] + d1[None, None, :] - eps
 
 
-def pcg(g, eps, iters, hgrid=(1.0, 1.0, 1.0), history=False):
+def pcg(g, eps, iters, hgrid=(1.0, 1.0, 1.0), history=False, bc="periodic"):
     """`iters` steps of preconditioned conjugate gradients on H_eps x = g from
     x = 0 with the diagonal preconditioner M = diag(H_eps):
 
@@ -69,7 +80,7 @@ def pcg(g, eps, iters, hgrid=(1.0, 1.0, 1.0), history=False):
 
     Returns (x, ||r||) after the last step, and the iterates if `history`."""
     g = np.asarray(g, dtype=np.float64)
-    diag = helmholtz_diagonal(g.shape, eps, hgrid)
+    diag = helmholtz_diagonal(g.shape, eps, hgrid, bc)
     x = np.zeros_like(g)
     r = g.copy()
     z = r / diag
@@ -77,7 +88,7 @@ def pcg(g, eps, iters, hgrid=(1.0, 1.0, 1.0), history=False):
     rz = float(np.sum(r * z))
     xs = [x.copy()]
     for _ in range(iters):
-        q = helmholtz(p, eps, hgrid)
+        q = helmholtz(p, eps, hgrid, bc)
         pq = float(np.sum(p * q))
         alpha = rz / pq if (pq > 0.0 and rz > 0.0) else 0.0
         x = x + alpha * p

@@ -114,3 +114,20 @@ def test_k0_form_of_the_kinetic_recursion():
     lhs = PC.helmholtz(c, eps, HG)
     rhs = W.analysis(W.kinetic(W.synthesis(c), HG)) - eps * c
     assert np.max(np.abs(lhs - rhs)) < 1e-14
+
+
+@pytest.mark.parametrize("bc", ["free", "surface"])
+def test_pcg_with_isolated_axes_reaches_the_dense_solution(F, bc):
+    """The Helmholtz operator of isolated / surface conditions: its dense
+    matrix (explicit-loop 1D matrices, zero potential) against PCG."""
+    from test_oracle_boundary import dense_hamiltonian
+    from oracle import boundary as BCo
+    dims, eps = (3, 2, 3), -0.45
+    shape = inputs.fine_shape(dims)
+    H = dense_hamiltonian(dims, bc, np.zeros(BCo.real_space_shape(dims, bc)), F, HG)
+    H = H - eps * np.eye(H.shape[0])
+    assert np.max(np.abs(PC.helmholtz_diagonal(shape, eps, HG, bc).ravel() - np.diag(H))) < 1e-13
+    g = _vec(12, shape)
+    ref = np.linalg.solve(H, g.ravel())
+    x, res = PC.pcg(g, eps, 150, HG, bc=bc)
+    assert np.linalg.norm(x.ravel() - ref) / np.linalg.norm(ref) < 1e-11
