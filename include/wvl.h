@@ -73,6 +73,23 @@ typedef enum { WVL_F64 = 0, WVL_F32 = 1, WVL_F32C = 2 } wvl_prec;
  * wvl_plan_tuning. */
 #define WVL_PERSISTENT 4u  /* persistent, work-queue launches (see above)        */
 #define WVL_AUTOTUNE   8u  /* time the launch candidates at plan creation       */
+/* Boundary conditions (Sec. 3.1; periodic when neither flag is set).
+ * WVL_FREE_BC: isolated along every axis; WVL_SURFACE_BC: isolated along
+ * axis 2, periodic along axes 1 and 3 (a slab).  Along an isolated axis the
+ * orbital has its m = 2n coefficients and nothing outside the box; the
+ * synthesis spreads them over m + 14 fine scaling coefficients and the magic
+ * filter over m + 29 real-space points, global positions -14 .. m + 14 of the
+ * fine grid (position 0: the first coefficient).  V and rho live on that
+ * real-space grid (wvl_plan_grid_points() points, C order (M3, M2, M1) with
+ * M_a = m_a + 29 along isolated axes).  Such plans need WVL_SHARED_V and a
+ * dense uniform batch; they run wvl_local_hpsi, wvl_local_density,
+ * wvl_energy_gradient, wvl_precondition (combined-filter form), the overlap
+ * and orthonormalisation and the compressed-storage calls, with one 1D pass
+ * per axis and operator (no plane kernel, no persistent launches, no tuner);
+ * wvl_synthesis, wvl_analysis, wvl_magic_filter and wvl_kinetic are
+ * periodic only (WVL_EUNSUPPORTED). */
+#define WVL_FREE_BC    16u
+#define WVL_SURFACE_BC 32u
 
 typedef struct {
   int32_t n[3];     /* coarse dims n1, n2, n3 (>= 2 each); fine dims are 2n     */

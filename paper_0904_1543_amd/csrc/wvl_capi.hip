@@ -74,7 +74,17 @@ struct wvl_plan {
   bool dense = false;    // off_b = b * M, all dims equal
   bool occ_uniform = true;  // every orbital has the same occupation
   int64_t M = 0;         // points per orbital when uniform
+  // boundary conditions (Sec. 3.1): isolated axes; real-space grid of V and
+  // rho (m_a + 29 points along isolated axes) and its points per orbital
+  bool bc_free[3] = {false, false, false};
+  bool bc_any = false;
+  int Mr[3] = {0, 0, 0};
+  int64_t Mrs = 0;
+  int bc_tiles[3] = {0, 0, 0};   // tiles per orbital of the kinetic passes, axes 1..3
+  OrbDev* d_orbs_rs = nullptr;   // real-space offsets (b * Mrs) for the pointwise stage
+  int32_t* d_pb = nullptr;       // prefixes b * bc_tiles[a] of the kinetic passes (3 arrays)
   int64_t elems = 0;     // elements per packed plane
+  int64_t elems_rs = 0;  // elements of a real-space batch array (per plane)
   int64_t vlen = 0;      // minimal length of a per-orbital V buffer
   std::vector<OrbDev> orbs;
   std::vector<int32_t> pz, py, px, pp, pq, pc;
@@ -164,11 +174,21 @@ struct Mark {
 
 static int esize(int prec) { return prec == WVL_F32 ? 4 : 8; }
 
+constexpr int kBcExtra = 29;   // real-space points added along an isolated axis
+
 constexpr int kQueueCounters = 16;   // work-queue counters per launch sequence
 constexpr int kTuneCands = 12;       // launch candidates of the tuner (4 sequences x 3 shapes)
 
 static int check_plan(const wvl_plan* p) {
   if (!p) return fail(WVL_EINVAL, "plan is NULL");
+  return WVL_OK;
+}
+
+// the single 3D transforms keep the array shape: periodic plans only
+static int check_periodic(const wvl_plan* p, const char* what) {
+  if (p->bc_any)
+    return fail(WVL_EUNSUPPORTED, "%s: periodic plans only (isolated axes change the array length)",
+                what);
   return WVL_OK;
 }
 
@@ -269,8 +289,11 @@ int wvl_plan_create(wvl_ctx* ctx, const wvl_orbital* orbs, int32_t norb, int32_t
   if (norb <= 0) return fail(WVL_EINVAL, "norb = %d must be positive", norb);
   if (!orbs) return fail(WVL_EINVAL, "orbs is NULL");
   if (prec < WVL_F64 || prec > WVL_F32C) return fail(WVL_EINVAL, "unknown precision %d", prec);
-  if (flags & ~(uint32_t)(WVL_SHARED_V | WVL_USE_GRAPH | WVL_PERSISTENT | WVL_AUTOTUNE))
+  if (flags & ~(uint32_t)(WVL_SHARED_V | WVL_USE_GRAPH | WVL_PERSISTENT | WVL_AUTOTUNE |
+                          WVL_FREE_BC | WVL_SURFACE_BC))
     return fail(WVL_EINVAL, "unknown flag bits 0x%x", flags);
+  if ((flags & WVL_FREE_BC) && (flags & WVL_SURFACE_BC))
+    return fail(WVL_EINVAL, "WVL_FREE_BC and WVL_SURFACE_BC exclude each other");
   wvl_plan* p = new wvl_plan();
   p->ctx = ctx;
   p->prec = prec;
@@ -307,10 +330,11 @@ int wvl_plan_create(wvl_ctx* ctx, const wvl_orbital* orbs, int32_t norb, int32_t
       // diagonal of A Kin S along this axis: the combined kinetic filter's
       // taps that map a coefficient onto itself on the periodic line
       // (offsets o = 0 mod m), for scaling (even) and wavelet (odd) outputs
+      const bool iso = (flags & WVL_FREE_BC) || ((flags & WVL_SURFACE_BC) && a == 1);
       for (int par = 0; par < 2; ++par) {
         double sum = 0.0;
         for (int off = WVL_CK_LO; off < WVL_CK_LO + WVL_CK_N; ++off)
-          if (off % d.m[a] == 0) sum += coef<OP_CK>(par, off, 0);
+          if (iso ? off == 0 : off % d.m[a] == 0) sum += coef<OP_CK>(par, off, 0);
         d.kdiag[a][par] = d.kscale[a] * sum;
       }
     }
@@ -341,6 +365,23 @@ int wvl_plan_create(wvl_ctx* ctx, const wvl_orbital* orbs, int32_t norb, int32_t
   p->dense = dense && uniform;
   for (int b = 1; b < norb; ++b)
     if (p->orbs[b].occ != p->orbs[0].occ) p->occ_uniform = false;
+  // boundary conditions: isolated along every axis, or along axis 2 (slab)
+  for (int a = 0; a < 3; ++a)
+    p->bc_free[a] = (flags & WVL_FREE_BC) || ((flags & WVL_SURFACE_BC) && a == 1);
+  p->bc_any = p->bc_free[0] || p->bc_free[1] || p->bc_free[2];
+  if (p->bc_any && !(p->shared && p->dense)) {
+    delete p;
+    return fail(WVL_EUNSUPPORTED,
+                "isolated/surface boundary conditions need WVL_SHARED_V and a dense uniform batch");
+  }
+  for (int a = 0; a < 3; ++a) p->Mr[a] = p->orbs[0].m[a] + (p->bc_free[a] ? kBcExtra : 0);
+  p->Mrs = uniform ? (int64_t)p->Mr[0] * p->Mr[1] * p->Mr[2] : 0;
+  if (p->bc_any) {
+    const int m1 = p->orbs[0].m[0], m2 = p->orbs[0].m[1], m3 = p->orbs[0].m[2];
+    p->bc_tiles[0] = (m2 * m3 + bc_rows_per_tile(OP_CK, m1) - 1) / bc_rows_per_tile(OP_CK, m1);
+    p->bc_tiles[1] = (m1 * m3 + kThreads - 1) / kThreads;
+    p->bc_tiles[2] = (m1 * m2 + kThreads - 1) / kThreads;
+  }
   p->M = uniform ? (int64_t)p->orbs[0].m[0] * p->orbs[0].m[1] * p->orbs[0].m[2] : 0;
   p->elems = end;
   if (end > ((int64_t)1 << 40)) { delete p; return fail(WVL_EINVAL, "batch too large"); }
@@ -368,7 +409,7 @@ int wvl_plan_create(wvl_ctx* ctx, const wvl_orbital* orbs, int32_t norb, int32_t
       return fail(WVL_EINVAL, "too many tiles");
     }
   }
-  p->nblk = p->shared ? (int)((p->M + kThreads - 1) / kThreads) : 0;
+  p->nblk = p->shared ? (int)((p->Mrs + kThreads - 1) / kThreads) : 0;
   // plane-resident path: every orbital's (m1, m2) plane must fit the kernel
   {
     for (int b = 0; b < norb; ++b) {
@@ -378,14 +419,14 @@ int wvl_plan_create(wvl_ctx* ctx, const wvl_orbital* orbs, int32_t norb, int32_t
     // float64 uses the matrix cores when the plane fits their tiling
     const bool mx = xy_matrix_engine(prec, p->xy_m1, p->xy_m2) && !getenv("WVL_XY_VECTOR");
     bool ok = xy_supported(prec, p->xy_m1, p->xy_m2, mx);
-    if (getenv("WVL_NO_PLANE_KERNEL")) ok = false;
+    if (getenv("WVL_NO_PLANE_KERNEL") || p->bc_any) ok = false;
     if (const char* o = getenv("WVL_PLANE_OCCUPANCY")) p->xy_occ = atoi(o) == 2 ? 2 : 4;
     // compensated float32 keeps two windows of hi/lo pairs: fused, it drops
     // to one wave per SIMD and is slower than the two passes
     p->zfuse = prec != WVL_F32C && !getenv("WVL_NO_ZFUSE");
     p->use_xy = ok;
-    p->xy_ok = xy_supported(prec, p->xy_m1, p->xy_m2, mx) ||
-               xy_supported(prec, p->xy_m1, p->xy_m2, false);
+    p->xy_ok = !p->bc_any && (xy_supported(prec, p->xy_m1, p->xy_m2, mx) ||
+                              xy_supported(prec, p->xy_m1, p->xy_m2, false));
     p->xy_engine = ok && mx ? 1 : 0;
     p->variant = ok ? 1 + p->xy_engine : 0;
     if (p->shared) {
@@ -434,20 +475,23 @@ int wvl_plan_create(wvl_ctx* ctx, const wvl_orbital* orbs, int32_t norb, int32_t
   }
   // workspace layout
   size_t off = 0;
-  const size_t arr = align256((size_t)p->elems * esize(prec));
+  // batch arrays: coefficients, or the real-space grid of isolated axes
+  p->elems_rs = p->bc_any ? (int64_t)norb * p->Mrs : p->elems;
+  const size_t arr = align256((size_t)std::max(p->elems, p->elems_rs) * esize(prec));
   p->o_A = off; off += arr;
   p->o_B = off; off += arr;
   p->o_S = off; off += arr;
   p->o_D = off; off += arr;      // fourth batch array: preconditioner, separate-pass form
   p->o_cg = off;                 // preconditioner: r.z, p.p, r.r tile partials, eps, scalars
   off += cg_bytes(p);
-  p->o_ez = off; off += align256(sizeof(double) * p->pz[norb]);
-  p->o_ey = off; off += align256(sizeof(double) * p->py[norb]);
-  p->o_ex = off; off += align256(sizeof(double) * std::max(p->px[norb], p->px2[norb]));
+  p->o_ez = off; off += align256(sizeof(double) * std::max<int64_t>(p->pz[norb], (int64_t)norb * p->bc_tiles[2]));
+  p->o_ey = off; off += align256(sizeof(double) * std::max<int64_t>(p->py[norb], (int64_t)norb * p->bc_tiles[1]));
+  p->o_ex = off; off += align256(sizeof(double) * std::max<int64_t>(std::max(p->px[norb], p->px2[norb]),
+                                                                   (int64_t)norb * p->bc_tiles[0]));
   p->o_pp = off;
   off += align256(sizeof(double) * (p->shared ? (size_t)norb * p->nblk : (size_t)p->pp[norb]));
   p->o_rv = off; off += align256(sizeof(double) * (size_t)std::max(p->nblk, 1));
-  p->o_rho = off; off += align256(sizeof(double) * (size_t)(p->shared ? p->M : 1));
+  p->o_rho = off; off += align256(sizeof(double) * (size_t)(p->shared ? p->Mrs : 1));
   p->o_eorb = off; off += align256(sizeof(double) * 2 * (size_t)norb);
   if (p->dense) {
     p->o_syrk = off; off += align256(sizeof(double) * (size_t)syrk_partials(norb, p->M));
@@ -513,7 +557,24 @@ int wvl_plan_create(wvl_ctx* ctx, const wvl_orbital* orbs, int32_t norb, int32_t
       return hipfail(e, "plan upload");
     }
   }
-  if ((flags & WVL_AUTOTUNE) && !ctx->dry) {
+  if (p->bc_any && !ctx->dry) {
+    std::vector<OrbDev> rs(p->orbs);
+    for (int b = 0; b < norb; ++b) rs[b].off = (int64_t)b * p->Mrs;
+    std::vector<int32_t> pb(3 * (size_t)(norb + 1));
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b <= norb; ++b) pb[(size_t)a * (norb + 1) + b] = b * p->bc_tiles[a];
+    hipError_t e = hipMalloc((void**)&p->d_orbs_rs, sizeof(OrbDev) * norb);
+    if (e == hipSuccess) e = hipMalloc((void**)&p->d_pb, sizeof(int32_t) * pb.size());
+    if (e == hipSuccess)
+      e = hipMemcpy(p->d_orbs_rs, rs.data(), sizeof(OrbDev) * norb, hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+      e = hipMemcpy(p->d_pb, pb.data(), sizeof(int32_t) * pb.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      wvl_plan_destroy(p);
+      return fail(WVL_ENOMEM, "boundary-condition tables: %s", hipGetErrorString(e));
+    }
+  }
+  if ((flags & WVL_AUTOTUNE) && !ctx->dry && !p->bc_any) {
     if (int r = autotune(p)) { wvl_plan_destroy(p); return r; }
   }
   *plan = p;
@@ -536,6 +597,8 @@ int wvl_plan_destroy(wvl_plan* p) {
     if (p->d_pz) (void)hipFree(p->d_pz);
     if (p->d_info) (void)hipFree(p->d_info);
     if (p->d_map_c) (void)hipFree(p->d_map_c);
+    if (p->d_orbs_rs) (void)hipFree(p->d_orbs_rs);
+    if (p->d_pb) (void)hipFree(p->d_pb);
   }
   delete p;
   return WVL_OK;
@@ -559,7 +622,7 @@ int wvl_plan_grid_points(const wvl_plan* p, int64_t* points) {
   if (int r = check_plan(p)) return r;
   if (!points) return fail(WVL_EINVAL, "points is NULL");
   if (!p->shared) return fail(WVL_EUNSUPPORTED, "plan has no shared grid");
-  *points = p->M;
+  *points = p->Mrs;
   return WVL_OK;
 }
 
@@ -647,6 +710,118 @@ struct Seq {
     if (_e != hipSuccess) return hipfail(_e, "kernel launch"); \
   } while (0)
 
+// ---------------------------------------------------------------------------
+// Isolated / surface boundary conditions (Sec. 3.1): pass-by-pass sequence on
+// arrays whose length along an isolated axis changes (m coefficients, m + 29
+// real-space points).  Real-space arrays in the workspace have the plane
+// stride elems_rs (compensated float32); coefficient arrays p->elems.
+// ---------------------------------------------------------------------------
+struct Shape { int n[3]; };   // lengths along axes 1, 2, 3
+
+hipError_t bc_pass(wvl_plan* p, hipStream_t st, int op, int axis, Shape& sh, const void* in,
+                   void* out, const void* k0, int64_t plane_in, int64_t plane_out,
+                   int64_t plane_k0, double kmul, double* ep) {
+  Mark mk(p, st, stage_of(op, axis));
+  const int a = axis - 1;
+  const bool iso = p->bc_free[a];
+  const int m = p->orbs[0].m[a];
+  BcPass g{};
+  g.orbs = p->d_orbs;
+  g.orbs_n = p->norb;
+  g.n1 = sh.n[0];
+  g.n2 = sh.n[1];
+  g.n3 = sh.n[2];
+  g.n_in = sh.n[a];
+  // global position of output 0 minus that of input 0: the real-space grid
+  // of an isolated axis starts 14 fine points before the coefficients
+  if (op == OP_CW) { g.n_out = iso ? m + kBcExtra : m; g.d = iso ? -14 : 0; }
+  else if (op == OP_CWT) { g.n_out = m; g.d = iso ? 14 : 0; }
+  else { g.n_out = m; g.d = 0; }
+  g.periodic = iso ? 0 : 1;
+  Shape o = sh;
+  o.n[a] = g.n_out;
+  g.vol_in = (int64_t)sh.n[0] * sh.n[1] * sh.n[2];
+  g.vol_out = (int64_t)o.n[0] * o.n[1] * o.n[2];
+  if (axis == 1) {
+    g.rows_per_tile = bc_rows_per_tile(op, g.n_out);
+    g.tiles = (sh.n[1] * sh.n[2] + g.rows_per_tile - 1) / g.rows_per_tile;
+  } else {
+    const int64_t lines = axis == 3 ? (int64_t)sh.n[0] * sh.n[1] : (int64_t)sh.n[0] * sh.n[2];
+    g.tiles = (int)((lines + kThreads - 1) / kThreads);
+  }
+  g.plane_k0 = plane_k0;
+  sh = o;
+  return launch_bc_pass(p->prec, op, axis, g, in, out, k0, plane_in, plane_out, kmul, ep, st);
+}
+
+// psi = W3 c on the real-space grid, into A (plane elems_rs)
+int bc_point_values(wvl_plan* p, hipStream_t st, const void* c, void* A, void* B) {
+  const int64_t prs = p->elems_rs;
+  Shape sh{{p->orbs[0].m[0], p->orbs[0].m[1], p->orbs[0].m[2]}};
+  WVL_CHK(bc_pass(p, st, OP_CW, 3, sh, c, A, nullptr, p->elems, prs, 0, 1.0, nullptr));
+  WVL_CHK(bc_pass(p, st, OP_CW, 2, sh, A, B, nullptr, prs, prs, 0, 1.0, nullptr));
+  WVL_CHK(bc_pass(p, st, OP_CW, 1, sh, B, A, nullptr, prs, prs, 0, 1.0, nullptr));
+  return WVL_OK;
+}
+
+// (K_x + K_y + K_z) c + k0 with the kinetic energies <c, K_a c> per tile
+int bc_kinetic(wvl_plan* p, hipStream_t st, const void* c, const void* k0, int64_t plane_k0,
+               void* tmp, int64_t plane_tmp, void* out, int64_t plane_out, double kmul,
+               double* ez, double* ey, double* ex) {
+  Shape sh{{p->orbs[0].m[0], p->orbs[0].m[1], p->orbs[0].m[2]}};
+  const Shape c_sh = sh;
+  WVL_CHK(bc_pass(p, st, OP_CK, 3, sh, c, tmp, k0, p->elems, plane_tmp, plane_k0, kmul, ez));
+  sh = c_sh;
+  WVL_CHK(bc_pass(p, st, OP_CK, 2, sh, c, tmp, tmp, p->elems, plane_tmp, plane_tmp, kmul, ey));
+  sh = c_sh;
+  WVL_CHK(bc_pass(p, st, OP_CK, 1, sh, c, out, tmp, p->elems, plane_out, plane_tmp, kmul, ex));
+  return WVL_OK;
+}
+
+int hpsi_bc(wvl_plan* p, hipStream_t st, const void* c, const double* V, double pot_scale,
+            double kin_scale, void* hpsi, double* rho, double* e_loc, double* e_kin, double* e_orb,
+            void* ws) {
+  void* A = wsp(ws, p->o_A);
+  void* B = wsp(ws, p->o_B);
+  void* S = wsp(ws, p->o_S);
+  double* ez = (double*)wsp(ws, p->o_ez);
+  double* ey = (double*)wsp(ws, p->o_ey);
+  double* ex = (double*)wsp(ws, p->o_ex);
+  double* pp = (double*)wsp(ws, p->o_pp);
+  double* rv = (double*)wsp(ws, p->o_rv);
+  double* eorb = e_orb ? e_orb : (double*)wsp(ws, p->o_eorb);
+  const bool want_e = e_loc || e_kin || e_orb;
+  const int64_t prs = p->elems_rs;
+  // steps 2 + 3a: psi on the real-space grid
+  if (int r = bc_point_values(p, st, c, A, B)) return r;
+  // step 3b and the density: y = pot_scale V psi in place
+  {
+    Mark mk(p, st, ST_POT);
+    WVL_CHK(launch_pot_shared(p->prec, p->d_orbs_rs, p->norb, p->Mrs, A, A, V, pot_scale, prs, rho,
+                              0, want_e ? rv : nullptr, e_orb ? pp : nullptr, st));
+  }
+  // steps 3c + 6: back onto the coefficients
+  Shape sh{{p->Mr[0], p->Mr[1], p->Mr[2]}};
+  WVL_CHK(bc_pass(p, st, OP_CWT, 1, sh, A, B, nullptr, prs, prs, 0, 1.0, nullptr));
+  WVL_CHK(bc_pass(p, st, OP_CWT, 2, sh, B, A, nullptr, prs, prs, 0, 1.0, nullptr));
+  WVL_CHK(bc_pass(p, st, OP_CWT, 3, sh, A, B, nullptr, prs, prs, 0, 1.0, nullptr));
+  // steps 4 + 5: the kinetic operator on the coefficients, accumulated onto B
+  if (int r = bc_kinetic(p, st, c, B, prs, S, prs, hpsi, p->elems, kin_scale,
+                         want_e ? ez : nullptr, want_e ? ey : nullptr, want_e ? ex : nullptr))
+    return r;
+  if (want_e) {
+    Mark mk(p, st, ST_ENERGY);
+    const int32_t* pbx = p->d_pb;
+    const int32_t* pby = p->d_pb + (p->norb + 1);
+    const int32_t* pbz = p->d_pb + 2 * (p->norb + 1);
+    WVL_CHK(launch_orb_sums(p->d_orbs, p->norb, pbz, pby, pbx, ez, ey, ex, pp, e_orb ? 2 : 0,
+                            p->d_pp, p->nblk, eorb, st));
+    if (e_loc || e_kin)
+      WVL_CHK(launch_totals(p->d_orbs, p->norb, eorb, rv, p->nblk, e_loc, e_kin, st));
+  }
+  return WVL_OK;
+}
+
 // The local H*psi launch sequence (Sec. 2.4 steps 2-6 with the density of
 // Sec. 2.5 and the float64 energies).  hpsi may be c itself: then the last z
 // step runs as two passes (the fused one would overwrite c at the start of a
@@ -654,6 +829,8 @@ struct Seq {
 int hpsi_sequence(wvl_plan* p, hipStream_t st, const void* c, const double* V, double pot_scale,
                   double kin_scale, void* hpsi, double* rho, double* e_loc, double* e_kin,
                   double* e_orb, void* ws) {
+  if (p->bc_any)
+    return hpsi_bc(p, st, c, V, pot_scale, kin_scale, hpsi, rho, e_loc, e_kin, e_orb, ws);
   Seq q(p, st);
   void* A = wsp(ws, p->o_A);
   void* B = wsp(ws, p->o_B);
@@ -822,7 +999,7 @@ int autotune(wvl_plan* p) {
   const bool seq_ok[4] = {true, plane_ok, plane_ok, mx && vec_ok};
   const size_t es = p->prec == WVL_F32 ? 4 : 8;
   const size_t arr = (size_t)p->elems * (p->prec == WVL_F32C ? 8 : es);
-  const size_t vbytes = sizeof(double) * (size_t)(p->shared ? p->M : std::max<int64_t>(p->vlen, 1));
+  const size_t vbytes = sizeof(double) * (size_t)(p->shared ? p->Mrs : std::max<int64_t>(p->vlen, 1));
   void *c = nullptr, *out = nullptr, *ws = nullptr, *V = nullptr, *e = nullptr;
   hipStream_t st = nullptr;
   hipEvent_t t0 = nullptr, t1 = nullptr;
@@ -895,6 +1072,7 @@ int wvl_synthesis(wvl_plan* p, const void* c, void* s, void* ws, void* stream) {
   if (int r = check_plan(p)) return r;
   if (!c || !s || !ws) return fail(WVL_EINVAL, "wvl_synthesis: NULL pointer");
   if (int r = check_disjoint(p, c, s, "wvl_synthesis")) return r;
+  if (int r = check_periodic(p, "wvl_synthesis")) return r;
   if (int r = check_gpu(p)) return r;
   Seq q(p, (hipStream_t)stream);
   WVL_CHK(q.op3(OP_SYN, c, s, wsp(ws, p->o_A)));
@@ -905,6 +1083,7 @@ int wvl_analysis(wvl_plan* p, const void* s, void* c, void* ws, void* stream) {
   if (int r = check_plan(p)) return r;
   if (!c || !s || !ws) return fail(WVL_EINVAL, "wvl_analysis: NULL pointer");
   if (int r = check_disjoint(p, s, c, "wvl_analysis")) return r;
+  if (int r = check_periodic(p, "wvl_analysis")) return r;
   if (int r = check_gpu(p)) return r;
   Seq q(p, (hipStream_t)stream);
   WVL_CHK(q.op3(OP_ANA, s, c, wsp(ws, p->o_A)));
@@ -916,6 +1095,7 @@ int wvl_magic_filter(wvl_plan* p, const void* in, void* out, int transpose, void
   if (int r = check_plan(p)) return r;
   if (!in || !out || !ws) return fail(WVL_EINVAL, "wvl_magic_filter: NULL pointer");
   if (int r = check_disjoint(p, in, out, "wvl_magic_filter")) return r;
+  if (int r = check_periodic(p, "wvl_magic_filter")) return r;
   if (int r = check_gpu(p)) return r;
   Seq q(p, (hipStream_t)stream);
   WVL_CHK(q.op3(transpose ? OP_MFT : OP_MF, in, out, wsp(ws, p->o_A)));
@@ -926,6 +1106,7 @@ int wvl_kinetic(wvl_plan* p, const void* s, const void* k0, void* out, void* ws,
   if (int r = check_plan(p)) return r;
   if (!s || !out || !ws) return fail(WVL_EINVAL, "wvl_kinetic: NULL pointer");
   if (int r = check_disjoint(p, s, out, "wvl_kinetic")) return r;
+  if (int r = check_periodic(p, "wvl_kinetic")) return r;
   if (k0 && overlap(k0, batch_bytes(p), s, batch_bytes(p)))
     return fail(WVL_EINVAL, "wvl_kinetic: k0 overlaps s");
   if (k0 && k0 != out && overlap(k0, batch_bytes(p), out, batch_bytes(p)))
@@ -948,6 +1129,12 @@ int wvl_local_density(wvl_plan* p, const void* c, double* rho, int accumulate, v
   Seq q(p, st);
   void* A = wsp(ws, p->o_A);
   void* B = wsp(ws, p->o_B);
+  if (p->bc_any) {
+    if (int r = bc_point_values(p, st, c, A, B)) return r;
+    WVL_CHK(launch_pot_shared(p->prec, p->d_orbs_rs, p->norb, p->Mrs, A, nullptr, nullptr, 1.0,
+                              p->elems_rs, rho, accumulate, nullptr, nullptr, st));
+    return WVL_OK;
+  }
   WVL_CHK(q.pass(OP_SYN, 3, c, A));
   WVL_CHK(q.pass(OP_SYN, 2, A, B));
   WVL_CHK(q.pass(OP_SYN, 1, B, B));
@@ -1039,6 +1226,8 @@ int wvl_precondition(wvl_plan* p, const void* g, const double* eps, int32_t iter
   if (iters < 0 || iters > 10000) return fail(WVL_EINVAL, "wvl_precondition: iters = %d", iters);
   if (mode & ~(uint32_t)WVL_PRECOND_SEPARATE)
     return fail(WVL_EINVAL, "wvl_precondition: unknown mode bits 0x%x", mode);
+  if (p->bc_any && (mode & WVL_PRECOND_SEPARATE))
+    return fail(WVL_EUNSUPPORTED, "wvl_precondition: the separate-pass form is periodic only");
   for (int b = 0; b < p->norb; ++b)
     if (!(eps[b] < 0.0) || !isfinite(eps[b]))
       return fail(WVL_EINVAL, "wvl_precondition: eps[%d] = %g must be negative and finite", b,
@@ -1068,7 +1257,9 @@ int wvl_precondition(wvl_plan* p, const void* g, const double* eps, int32_t iter
   WVL_CHK(launch_cg_init(p->prec, gp, nt, g, gt, R, Pv, eps_d, plane, prz, ppp, prr, st));
   for (int it = 0; it < iters; ++it) {
     // q = (A Kin S - eps) p, with the kinetic energy partials p.Kin p
-    if (!separate) {
+    if (p->bc_any) {
+      if (int r = bc_kinetic(p, st, Pv, nullptr, plane, Q, plane, Q, plane, 1.0, ez, ey, ex)) return r;
+    } else if (!separate) {
       // combined filter (analysis o kinetic o synthesis) per axis, on the
       // coefficients; q = Kin p here, the shift is applied in the update
       WVL_CHK(q.pass(OP_CK, 3, Pv, Q, nullptr, 1.0, ez));
@@ -1086,8 +1277,12 @@ int wvl_precondition(wvl_plan* p, const void* g, const double* eps, int32_t iter
     }
     {
       Mark mk(p, st, ST_CG);
-      WVL_CHK(launch_cg_alpha(p->norb, p->d_pz, p->d_py, p->xdiv == 2 ? p->d_px2 : p->d_px, p->d_pc,
-                              ez, ey, ex, prz, ppp, eps_d, sc, st));
+      if (p->bc_any)
+        WVL_CHK(launch_cg_alpha(p->norb, p->d_pb + 2 * (p->norb + 1), p->d_pb + (p->norb + 1), p->d_pb,
+                                p->d_pc, ez, ey, ex, prz, ppp, eps_d, sc, st));
+      else
+        WVL_CHK(launch_cg_alpha(p->norb, p->d_pz, p->d_py, p->xdiv == 2 ? p->d_px2 : p->d_px,
+                                p->d_pc, ez, ey, ex, prz, ppp, eps_d, sc, st));
       WVL_CHK(launch_cg_update1(p->prec, gp, nt, gt, R, Pv, Q, eps_d, separate ? 0 : 1, sc, plane,
                                 prz, prr, st));
       WVL_CHK(launch_cg_beta(p->norb, p->d_pc, prz, sc, st));

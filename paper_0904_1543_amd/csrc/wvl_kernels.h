@@ -81,6 +81,28 @@ hipError_t launch_cg_shift(int prec, const PassGeom& g, int ntiles, const void* 
 hipError_t launch_cg_res(int norb, const int32_t* pp, const double* prr, double* res,
                          hipStream_t st);
 
+// 1D pass with isolated or periodic boundary conditions (wvl_bc.hip) on a
+// uniform batch: input arrays (n3, n2, n1) with the pass axis of length n_in,
+// output the same with n_out; y[k] = sum_o F(o) x[k + d - o], zero outside the
+// input (isolated) or wrapped (periodic, d = 0, n_in = n_out).  Batch stride
+// vol_in / vol_out; `tiles` tiles per orbital (256 lines, or rows_per_tile
+// rows along axis 1); k0 (nullable) is in the output shape, with its own
+// plane stride.
+struct BcPass {
+  const OrbDev* orbs;
+  int32_t orbs_n;
+  int32_t n1, n2, n3;      // dims of the arrays along the axes other than the pass
+  int32_t n_in, n_out, d;
+  int32_t periodic;
+  int64_t vol_in, vol_out;
+  int32_t tiles, rows_per_tile;
+  int64_t plane_k0;        // compensated float32: plane stride of k0
+};
+int bc_rows_per_tile(int op, int n_out);
+hipError_t launch_bc_pass(int prec, int op, int axis, const BcPass& g, const void* in, void* out,
+                          const void* k0, int64_t plane_in, int64_t plane_out, double kmul,
+                          double* epart, hipStream_t st);
+
 // Compressed storage (wvl_compress.hip): uniform batch of norb orbitals of M
 // points; compressed vectors of L = nvc + 7 nvf values at b * L.
 hipError_t launch_decompress(int prec, const OrbDev* orbs, int norb, int64_t M,

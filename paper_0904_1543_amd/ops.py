@@ -46,7 +46,8 @@ class Plan:
     """A batch of orbitals with given coarse dims (n1, n2, n3) per orbital."""
 
     def __init__(self, dims, prec="f64", shared_v=True, hgrid=(1.0, 1.0, 1.0), occ=2.0,
-                 graph=False, persistent=False, autotune=False, device=0, dry=False):
+                 graph=False, persistent=False, autotune=False, device=0, dry=False,
+                 bc="periodic"):
         self.dims = [tuple(int(v) for v in d) for d in dims]
         self.norb = len(self.dims)
         self.prec = prec
@@ -71,7 +72,9 @@ class Plan:
             arr[b].occ = float(occs[b])
         self.occ = np.array(occs, dtype=np.float64)
         flags = (lib.WVL_SHARED_V if shared_v else 0) | (lib.WVL_USE_GRAPH if graph else 0) | \
-            (lib.WVL_PERSISTENT if persistent else 0) | (lib.WVL_AUTOTUNE if autotune else 0)
+            (lib.WVL_PERSISTENT if persistent else 0) | (lib.WVL_AUTOTUNE if autotune else 0) | \
+            {"periodic": 0, "free": lib.WVL_FREE_BC, "surface": lib.WVL_SURFACE_BC}[bc]
+        self.bc = bc
         self._arr = arr
         ctx = ctypes.c_void_p()
         if dry:
@@ -90,6 +93,12 @@ class Plan:
         lib.wvl_plan_elements(h, ctypes.byref(el))
         self.ws_bytes = wsb.value
         self.elems = el.value
+        # points of V and rho (the real-space grid of a shared potential)
+        self.grid_points = self.M[0]
+        if shared_v:
+            gp = ctypes.c_int64()
+            lib.wvl_plan_grid_points(h, ctypes.byref(gp))
+            self.grid_points = gp.value
         self.ws = None
         if not dry:
             self.ws = torch.empty(max(self.ws_bytes, 256), dtype=torch.uint8,
@@ -177,7 +186,7 @@ class Plan:
         return out
 
     def local_density(self, c, rho=None, accumulate=False):
-        npts = self.M[0]
+        npts = self.grid_points
         if rho is None:
             rho = torch.empty(npts, dtype=torch.float64, device=self.dev)
         lib.wvl_local_density(self.h, ptr(c), ptr(rho), int(bool(accumulate)), ptr(self.ws),
@@ -187,7 +196,7 @@ class Plan:
     def local_hpsi(self, c, V, pot_scale=1.0, kin_scale=1.0, out=None, rho=True, energies=True,
                    per_orbital=False):
         out = self.empty() if out is None else out
-        r = torch.empty(self.M[0], dtype=torch.float64, device=self.dev) \
+        r = torch.empty(self.grid_points, dtype=torch.float64, device=self.dev) \
             if (rho and self.shared_v) else None
         e = torch.empty(2, dtype=torch.float64, device=self.dev) if energies else None
         eo = torch.empty(2 * self.norb, dtype=torch.float64, device=self.dev) if per_orbital else None
@@ -263,7 +272,7 @@ class Plan:
     def local_hpsi_compressed(self, psi_c, V, pot_scale=1.0, kin_scale=1.0, out=None, rho=True,
                               energies=True, per_orbital=False):
         out = self.empty_compressed() if out is None else out
-        r = torch.empty(self.M[0], dtype=torch.float64, device=self.dev) \
+        r = torch.empty(self.grid_points, dtype=torch.float64, device=self.dev) \
             if (rho and self.shared_v) else None
         e = torch.empty(2, dtype=torch.float64, device=self.dev) if energies else None
         eo = torch.empty(2 * self.norb, dtype=torch.float64, device=self.dev) if per_orbital else None

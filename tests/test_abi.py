@@ -247,3 +247,24 @@ def test_region_checks(dry):
     rc, p = _plan(dry, [(4, 4, 4), (4, 6, 4)], flags=0)                 # uneven batch
     assert f(p, good, n, good, n) == lib.WVL_EUNSUPPORTED
     lib.wvl_plan_destroy(p)
+
+
+def test_boundary_condition_plans(dry):
+    a, b, ws = ctypes.c_void_p(0x100000), ctypes.c_void_p(0x200000), ctypes.c_void_p(0x300000)
+    assert _plan(dry, [(4, 4, 4)] * 2, flags=1 | 16 | 32)[0] == lib.WVL_EINVAL     # both
+    assert _plan(dry, [(4, 4, 4)] * 2, flags=16)[0] == lib.WVL_EUNSUPPORTED       # no shared V
+    assert _plan(dry, [(4, 4, 4), (4, 6, 4)], flags=16)[0] == lib.WVL_EUNSUPPORTED
+    for flag, shape in ((16, (37, 37, 37)), (32, (8, 37, 8))):
+        rc, p = _plan(dry, [(4, 4, 4)] * 2, flags=1 | flag)
+        assert rc == lib.WVL_OK
+        pts = ctypes.c_int64()
+        lib.wvl_plan_grid_points(p, ctypes.byref(pts))
+        assert pts.value == shape[0] * shape[1] * shape[2]        # m + 29 on isolated axes
+        assert lib.raw("wvl_synthesis")(p, a, b, ws, None) == lib.WVL_EUNSUPPORTED
+        assert lib.raw("wvl_kinetic")(p, a, None, b, ws, None) == lib.WVL_EUNSUPPORTED
+        assert lib.raw("wvl_local_hpsi")(p, a, b, 1.0, 1.0, ws, None, None, None, None, ws,
+                                          None) == lib.WVL_ENODEV
+        eps = (ctypes.c_double * 2)(-0.5, -0.2)
+        assert lib.raw("wvl_precondition")(p, a, eps, 3, 1, b, None, ws, None) == \
+            lib.WVL_EUNSUPPORTED                                   # separate form: periodic only
+        lib.wvl_plan_destroy(p)
