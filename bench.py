@@ -246,7 +246,9 @@ PRECOND_ITERS = 5
 def run_precond(C, dims, steps, warmup, check):
     """The preconditioner (Sec. 2, Eq. "precon") on the same batch: 5 steps of
     preconditioned conjugate gradients per call, float64 and compensated
-    float32, the combined-filter form and the separate-pass form of the
+    float32, in three forms: the fused wavelet + kinetic operator with both
+    in-plane axes in one plane-resident kernel, the combined filter one pass
+    per axis, and the separate synthesis / kinetic / analysis passes of the
     paper's GPU design.  Inputs: the batch's coefficients as gradients, one
     orbital energy per orbital uniform in [-1, -0.1]."""
     import torch
@@ -267,15 +269,16 @@ def run_precond(C, dims, steps, warmup, check):
         plan = ops.Plan(dims, prec=prec)
         g = plan.pack(C)
         gt = plan.empty()
-        for form, sep in (("combined_filter", False), ("separate_passes", True)):
+        for name, form in (("fused_plane_kernel", None), ("combined_filter_passes", "passes"),
+                           ("separate_passes", "separate")):
             for _ in range(max(1, warmup)):
-                plan.precondition(g, eps, PRECOND_ITERS, separate=sep, out=gt)
+                plan.precondition(g, eps, PRECOND_ITERS, form=form, out=gt)
             torch.cuda.synchronize()
             t0 = torch.cuda.Event(enable_timing=True)
             t1 = torch.cuda.Event(enable_timing=True)
             t0.record()
             for _ in range(steps):
-                plan.precondition(g, eps, PRECOND_ITERS, separate=sep, out=gt)
+                plan.precondition(g, eps, PRECOND_ITERS, form=form, out=gt)
             t1.record()
             torch.cuda.synchronize()
             ms = t0.elapsed_time(t1) / steps
@@ -291,7 +294,7 @@ def run_precond(C, dims, steps, warmup, check):
                     den += float(np.sum(refs[b] ** 2))
                 rec["rel_err_vs_oracle"] = {"orbitals": sample, "normwise": (num / den) ** 0.5,
                                             "tolerance": TOL[prec]}
-            out[f"{prec}/{form}"] = rec
+            out[f"{prec}/{name}"] = rec
         del plan, g, gt
         torch.cuda.empty_cache()
     return out

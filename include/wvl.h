@@ -229,9 +229,12 @@ int wvl_energy_gradient(wvl_plan *plan, const void *c, const double *V, double g
  *   eps   HOST array of norb doubles, copied before the call returns
  *   mode  0: the operator as one combined filter per axis (synthesis,
  *         kinetic filter and analysis composed, Sec. 2.4 last paragraph and
- *         Sec. 6.1: the fused form); WVL_PRECOND_SEPARATE: the separate 3D
- *         synthesis, kinetic (with K_0) and analysis passes of the paper's
- *         GPU design (Sec. 2.4, Sec. 3.4)
+ *         Sec. 6.1: the fused wavelet + kinetic kernel), with both in-plane
+ *         axes applied by one plane-resident kernel when the plane fits it
+ *         (periodic plans), else one pass per axis; WVL_PRECOND_PASSES: the
+ *         combined filter, one pass per axis; WVL_PRECOND_SEPARATE: the
+ *         separate 3D synthesis, kinetic (with K_0) and analysis passes of
+ *         the paper's GPU design (Sec. 2.4, Sec. 3.4)
  *   gt    output batch array, must not overlap g (WVL_EINVAL)
  *   res   nullable device array of norb doubles: the residual norm
  *         ||g_b - H gt_b|| of the recurrence after the last step
@@ -239,6 +242,7 @@ int wvl_energy_gradient(wvl_plan *plan, const void *c, const double *V, double g
  * and scalars in float64.  Ordinary (not persistent) launches; not recorded
  * in the plan's graph. */
 #define WVL_PRECOND_SEPARATE 1u
+#define WVL_PRECOND_PASSES   2u
 int wvl_precondition(wvl_plan *plan, const void *g, const double *eps, int32_t iters,
                      uint32_t mode, void *gt, double *res, void *ws, void *stream);
 

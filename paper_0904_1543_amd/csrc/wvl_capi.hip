@@ -140,7 +140,7 @@ struct wvl_plan {
 
 // Stage ids for profiling: 1D passes are op * 3 + (axis - 1); then:
 enum { ST_POT = 15, ST_ENERGY = 16, ST_OVERLAP = 17, ST_CHOL = 18, ST_TRMM = 19, ST_XY = 29,
-       ST_RHO = 30, ST_ZFIN = 31, ST_CG = 32, ST_NSTAGE = 33 };
+       ST_RHO = 30, ST_ZFIN = 31, ST_CG = 32, ST_HELM = 33, ST_NSTAGE = 34 };
 static int stage_of(int op, int axis) {
   return op < 5 ? op * 3 + axis - 1 : 20 + (op - 5) * 3 + axis - 1;
 }
@@ -148,7 +148,7 @@ static const char* kStageNames[ST_NSTAGE] = {
     "mf_x", "mf_y", "mf_z", "mft_x", "mft_y", "mft_z", "syn_x", "syn_y", "syn_z",
     "ana_x", "ana_y", "ana_z", "kin_x", "kin_y", "kin_z", "potential", "energies",
     "overlap", "cholesky", "trmm", "cw_x", "cw_y", "cw_z", "cwt_x", "cwt_y", "cwt_z",
-    "ck_x", "ck_y", "ck_z", "xy_plane", "rho_reduce", "z_final", "cg_update"};
+    "ck_x", "ck_y", "ck_z", "xy_plane", "rho_reduce", "z_final", "cg_update", "helm_plane"};
 
 namespace {
 struct Mark {
@@ -1224,8 +1224,10 @@ int wvl_precondition(wvl_plan* p, const void* g, const double* eps, int32_t iter
   if (int r = check_plan(p)) return r;
   if (!g || !eps || !gt || !ws) return fail(WVL_EINVAL, "wvl_precondition: NULL pointer");
   if (iters < 0 || iters > 10000) return fail(WVL_EINVAL, "wvl_precondition: iters = %d", iters);
-  if (mode & ~(uint32_t)WVL_PRECOND_SEPARATE)
+  if (mode & ~(uint32_t)(WVL_PRECOND_SEPARATE | WVL_PRECOND_PASSES))
     return fail(WVL_EINVAL, "wvl_precondition: unknown mode bits 0x%x", mode);
+  if ((mode & WVL_PRECOND_SEPARATE) && (mode & WVL_PRECOND_PASSES))
+    return fail(WVL_EINVAL, "wvl_precondition: WVL_PRECOND_SEPARATE and WVL_PRECOND_PASSES exclude each other");
   if (p->bc_any && (mode & WVL_PRECOND_SEPARATE))
     return fail(WVL_EUNSUPPORTED, "wvl_precondition: the separate-pass form is periodic only");
   for (int b = 0; b < p->norb; ++b)
@@ -1253,12 +1255,24 @@ int wvl_precondition(wvl_plan* p, const void* g, const double* eps, int32_t iter
   const int nt = p->pc[p->norb];
   const int64_t plane = p->elems;
   const bool separate = (mode & WVL_PRECOND_SEPARATE) != 0;
+  // the plane-resident form: z pass, then both in-plane passes with the plane
+  // of p in LDS (periodic plans whose planes fit the in-plane kernel)
+  const bool helm_mx = xy_matrix_engine(p->prec, p->xy_m1, p->xy_m2) && !getenv("WVL_XY_VECTOR");
+  const bool plane_form = !separate && !(mode & WVL_PRECOND_PASSES) && !p->bc_any && p->xy_ok &&
+                          xy_supported(p->prec, p->xy_m1, p->xy_m2, helm_mx);
+  double* kpl = plane_form ? (double*)wsp(ws, p->o_kpl) : nullptr;
   WVL_HIP(hipMemcpyAsync(eps_d, eps, sizeof(double) * p->norb, hipMemcpyHostToDevice, st));
   WVL_CHK(launch_cg_init(p->prec, gp, nt, g, gt, R, Pv, eps_d, plane, prz, ppp, prr, st));
   for (int it = 0; it < iters; ++it) {
     // q = (A Kin S - eps) p, with the kinetic energy partials p.Kin p
     if (p->bc_any) {
       if (int r = bc_kinetic(p, st, Pv, nullptr, plane, Q, plane, Q, plane, 1.0, ez, ey, ex)) return r;
+    } else if (plane_form) {
+      // K_z p by the z pass, then (K_x + K_y) p added plane by plane
+      WVL_CHK(q.pass(OP_CK, 3, Pv, Q, nullptr, 1.0, ez));
+      Mark mk(p, st, ST_HELM);
+      HelmArgs ha{p->d_orbs, p->d_pq, p->norb, Pv, Q, plane, kpl};
+      WVL_CHK(launch_helm_xy(p->prec, ha, p->xy_m1, p->xy_m2, p->pq[p->norb], helm_mx, st));
     } else if (!separate) {
       // combined filter (analysis o kinetic o synthesis) per axis, on the
       // coefficients; q = Kin p here, the shift is applied in the update
@@ -1280,6 +1294,9 @@ int wvl_precondition(wvl_plan* p, const void* g, const double* eps, int32_t iter
       if (p->bc_any)
         WVL_CHK(launch_cg_alpha(p->norb, p->d_pb + 2 * (p->norb + 1), p->d_pb + (p->norb + 1), p->d_pb,
                                 p->d_pc, ez, ey, ex, prz, ppp, eps_d, sc, st));
+      else if (plane_form)
+        WVL_CHK(launch_cg_alpha(p->norb, p->d_pz, p->d_pq, nullptr, p->d_pc, ez, kpl, nullptr, prz,
+                                ppp, eps_d, sc, st));
       else
         WVL_CHK(launch_cg_alpha(p->norb, p->d_pz, p->d_py, p->xdiv == 2 ? p->d_px2 : p->d_px,
                                 p->d_pc, ez, ey, ex, prz, ppp, eps_d, sc, st));

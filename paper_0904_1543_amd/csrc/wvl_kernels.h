@@ -164,6 +164,21 @@ struct XyArgs {
   int32_t* queue;
   int32_t ntiles;
 };
+// In-plane part of the preconditioner's operator: kq += (K_x + K_y) p for
+// every (orbital, z-plane) (one workgroup each, slots pq[b] + z), with
+// ekin[slot] = <p, (K_x + K_y) p> over the plane.
+struct HelmArgs {
+  const OrbDev* orbs;
+  const int32_t* pq;
+  int32_t norb;
+  const void* p;
+  void* kq;
+  int64_t plane;
+  double* ekin;
+};
+hipError_t launch_helm_xy(int prec, const HelmArgs& a, int m1, int m2, int nblocks, bool engine,
+                          hipStream_t st);
+
 // engine: the float64 matrix-core form of the in-plane passes
 bool xy_matrix_engine(int prec, int m1, int m2);
 size_t xy_lds_bytes(int prec, int m1, int m2, bool engine);

@@ -24,11 +24,14 @@ namespace wvl {
 struct CgScal { double alpha, beta, rz, pad; };
 
 // Tiles of the element kernels: kCgTile consecutive elements of one orbital,
-// kCgPer per thread at a stride of kThreads (coalesced).  Each thread walks
-// its elements with the (x, y, z) position stepped incrementally, so the
-// diagonal needs no division per element.
-constexpr int kCgPer = 8;
-constexpr int kCgTile = kThreads * kCgPer;
+// in chunks of kCgPer per thread at a stride of kThreads (coalesced); the
+// loads of a chunk are issued before any is used, and a tile is long enough
+// to amortise the lookup of its orbital.  Each thread walks its elements with
+// the (x, y, z) position stepped incrementally, so the diagonal needs no
+// division per element.
+constexpr int kCgPer = 8;                      // elements per thread and chunk
+constexpr int kCgChunks = 4;                   // chunks per tile
+constexpr int kCgTile = kThreads * kCgPer * kCgChunks;
 
 struct CgPos {
   int x, y, z, dx, dy, dz, m1, m2;
@@ -70,8 +73,8 @@ __global__ __launch_bounds__(kThreads) void k_cg_init(PassGeom g, const void* gi
   const double ep = eps[b];
   double rz = 0.0, pp = 0.0, rr = 0.0;
   CgPos pos(od, e0);
-  #pragma unroll
-  for (int k = 0; k < kCgPer; ++k) {
+  #pragma unroll 1
+  for (int k = 0; k < kCgPer * kCgChunks; ++k) {
     const uint32_t e = e0 + (uint32_t)k * kThreads;
     if (e < M) {
       const int64_t i = od.off + e;
@@ -147,21 +150,38 @@ __global__ __launch_bounds__(kThreads) void k_cg_update1(PassGeom g, void* x, vo
   const double sh = shift ? ep : 0.0;
   double rz = 0.0, rr = 0.0;
   CgPos pos(od, e0);
+  #pragma unroll 1
+  for (int ch = 0; ch < kCgChunks; ++ch) {
+  const uint32_t c0 = e0 + (uint32_t)(ch * kCgPer) * kThreads;
+  // every load of the chunk is issued before the first use
+  double pv[kCgPer], qv[kCgPer], xv[kCgPer], rv[kCgPer];
   #pragma unroll
   for (int k = 0; k < kCgPer; ++k) {
-    const uint32_t e = e0 + (uint32_t)k * kThreads;
+    const uint32_t e = c0 + (uint32_t)k * kThreads;
+    pv[k] = qv[k] = xv[k] = rv[k] = 0.0;
     if (e < M) {
       const int64_t i = od.off + e;
-      const double pv = T::d(T::ldc(p, i, plane));
-      const double qv = T::d(T::ldc(q, i, plane)) - sh * pv;
-      const double xv = T::d(T::ldc(x, i, plane)) + a * pv;
-      const double rv = T::d(T::ldc(r, i, plane)) - a * qv;
-      T::st(x, i, plane, T::from_d(xv));
-      T::st(r, i, plane, T::from_d(rv));
-      rz += rv * (rv / pos.diag(od, ep));
-      rr += rv * rv;
+      pv[k] = T::d(T::ldc(p, i, plane));
+      qv[k] = T::d(T::ldc(q, i, plane));
+      xv[k] = T::d(T::ldc(x, i, plane));
+      rv[k] = T::d(T::ldc(r, i, plane));
+    }
+  }
+  #pragma unroll
+  for (int k = 0; k < kCgPer; ++k) {
+    const uint32_t e = c0 + (uint32_t)k * kThreads;
+    if (e < M) {
+      const int64_t i = od.off + e;
+      const double qs = qv[k] - sh * pv[k];
+      const double xn = xv[k] + a * pv[k];
+      const double rn = rv[k] - a * qs;
+      T::st(x, i, plane, T::from_d(xn));
+      T::st(r, i, plane, T::from_d(rn));
+      rz += rn * (rn / pos.diag(od, ep));
+      rr += rn * rn;
     }
     pos.next();
+  }
   }
   block_sum_store(rz, prz + blockIdx.x);
   block_sum_store(rr, prr + blockIdx.x);
@@ -193,17 +213,31 @@ __global__ __launch_bounds__(kThreads) void k_cg_update2(PassGeom g, const void*
   const double beta = sc[b].beta, ep = eps[b];
   double pp = 0.0;
   CgPos pos(od, e0);
+  #pragma unroll 1
+  for (int ch = 0; ch < kCgChunks; ++ch) {
+  const uint32_t c0 = e0 + (uint32_t)(ch * kCgPer) * kThreads;
+  double rv[kCgPer], pv[kCgPer];
   #pragma unroll
   for (int k = 0; k < kCgPer; ++k) {
-    const uint32_t e = e0 + (uint32_t)k * kThreads;
+    const uint32_t e = c0 + (uint32_t)k * kThreads;
+    rv[k] = pv[k] = 0.0;
     if (e < M) {
       const int64_t i = od.off + e;
-      const double z = T::d(T::ldc(r, i, plane)) / pos.diag(od, ep);
-      const double pv = z + beta * T::d(T::ldc(p, i, plane));
-      T::st(p, i, plane, T::from_d(pv));
-      pp += pv * pv;
+      rv[k] = T::d(T::ldc(r, i, plane));
+      pv[k] = T::d(T::ldc(p, i, plane));
+    }
+  }
+  #pragma unroll
+  for (int k = 0; k < kCgPer; ++k) {
+    const uint32_t e = c0 + (uint32_t)k * kThreads;
+    if (e < M) {
+      const int64_t i = od.off + e;
+      const double pn = rv[k] / pos.diag(od, ep) + beta * pv[k];
+      T::st(p, i, plane, T::from_d(pn));
+      pp += pn * pn;
     }
     pos.next();
+  }
   }
   block_sum_store(pp, ppp + blockIdx.x);
 }
@@ -219,8 +253,8 @@ __global__ __launch_bounds__(kThreads) void k_cg_shift(PassGeom g, const void* s
   const OrbDev od = g.orbs[b];
   const uint32_t M = (uint32_t)od.m[0] * od.m[1] * od.m[2];
   const double f = -eps[b];
-  #pragma unroll
-  for (int k = 0; k < kCgPer; ++k) {
+  #pragma unroll 4
+  for (int k = 0; k < kCgPer * kCgChunks; ++k) {
     const uint32_t e = (uint32_t)t * kCgTile + (uint32_t)k * kThreads + threadIdx.x;
     if (e < M) {
       const int64_t i = od.off + e;

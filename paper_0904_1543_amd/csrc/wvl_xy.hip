@@ -9,6 +9,9 @@ template <int P, bool SH>
 void xy_launch_v(const XyArgs& a, int mi, int nblocks, size_t lds, hipStream_t st);
 template <bool SH>
 void xy_launch_m(const XyArgs& a, int mt, int nblocks, size_t lds, hipStream_t st);
+template <int P>
+void helm_launch_v(const HelmArgs& a, int mi, int nblocks, size_t lds, hipStream_t st);
+void helm_launch_mf(const HelmArgs& a, int mt, int nblocks, size_t lds, hipStream_t st);
 
 // rho[r] = sum_g rho_part[g][r] (group order), and per-block sums of V rho
 __global__ __launch_bounds__(kThreads) void k_rho_reduce(const double* __restrict__ part, int ngroups,
@@ -63,6 +66,24 @@ hipError_t launch_xy(int prec, const XyArgs& a, int m1, int m2, int nblocks, hip
     case F64: sh ? xy_launch_v<F64, true>(a, mi, nblocks, lds, st) : xy_launch_v<F64, false>(a, mi, nblocks, lds, st); break;
     case F32: sh ? xy_launch_v<F32, true>(a, mi, nblocks, lds, st) : xy_launch_v<F32, false>(a, mi, nblocks, lds, st); break;
     default:  sh ? xy_launch_v<F32C, true>(a, mi, nblocks, lds, st) : xy_launch_v<F32C, false>(a, mi, nblocks, lds, st); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_helm_xy(int prec, const HelmArgs& a, int m1, int m2, int nblocks, bool engine,
+                          hipStream_t st) {
+  if (nblocks == 0) return hipSuccess;
+  if (engine && !xy_matrix_engine(prec, m1, m2)) return hipErrorInvalidValue;
+  const size_t lds = xy_lds_bytes(prec, m1, m2, engine);
+  if (engine) {
+    helm_launch_mf(a, xy_tiles(m1, m2), nblocks, lds, st);
+    return hipGetLastError();
+  }
+  const int mi = xy_items(m1, m2);
+  switch (prec) {
+    case F64: helm_launch_v<F64>(a, mi, nblocks, lds, st); break;
+    case F32: helm_launch_v<F32>(a, mi, nblocks, lds, st); break;
+    default:  helm_launch_v<F32C>(a, mi, nblocks, lds, st); break;
   }
   return hipGetLastError();
 }

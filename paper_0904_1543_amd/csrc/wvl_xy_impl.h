@@ -203,6 +203,7 @@ struct VecEngine {
   using V = typename T::V;
   struct Res { V r[MI][kU]; int n; };
   static constexpr bool kGroupLoop = false;   // one launch per slot
+  static constexpr bool kFusedK = false;      // in-plane kinetic passes through memory
   __device__ __forceinline__ static int pitch(int m1) { return m1 + 1; }
   template <int OP, int AX>
   __device__ __forceinline__ static void conv(V* buf, int m1, int m2, int pitch, Res& r) {
@@ -232,6 +233,24 @@ struct VecEngine {
       for (int u = 0; u < kU; ++u) {
         const int y = itr.seg * kU + u;
         if (y < m2) T::st(dst, gp + (int64_t)y * m1 + itr.line, plane, r.r[it][u]);
+      }
+      itr.next();
+    }
+  }
+  // dst += the results of an AX = 2 pass
+  __device__ __forceinline__ static void add_global_y(void* dst, int64_t gp, int64_t plane, int m1,
+                                                      int m2, const Res& r) {
+    ItemIter itr(m1);
+    #pragma unroll
+    for (int it = 0; it < MI; ++it) {
+      if (it >= r.n) break;
+      #pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        const int y = itr.seg * kU + u;
+        if (y < m2) {
+          const int64_t i = gp + (int64_t)y * m1 + itr.line;
+          T::st(dst, i, plane, T::plus(T::ldc(dst, i, plane), r.r[it][u]));
+        }
       }
       itr.next();
     }
@@ -276,6 +295,11 @@ struct MfEngine {
   using V = double;
   struct Res { d4 r[MT]; int n; };
   static constexpr bool kGroupLoop = true;    // a group's orbitals in one workgroup
+  // (K_x + K_y) c summed in the accumulators: both passes enumerate their
+  // tiles by (y block, x block), so a lane holds the same plane element in
+  // the y-pass and the x-pass result (element (i, n) of a tile: y offset i,
+  // x offset n in both), and the x pass starts from the y pass's sums
+  static constexpr bool kFusedK = true;
   // rows of 4 (mod 32) doubles: the x-pass operand (16 rows x 4 columns) and
   // the tile stores fall on distinct banks
   __device__ __forceinline__ static int pitch(int m1) { return m1 + ((36 - (m1 & 31)) & 31); }
@@ -286,8 +310,20 @@ struct MfEngine {
     k0 = bc * 16;
     o0 = (tile - bc * nbo) * 16;
   }
-  template <int OP, int AX>
-  __device__ __forceinline__ static void conv(V* buf, int m1, int m2, int pitch, Res& r) {
+  // tile t of this wave in (y block, x block) order for both passes
+  __device__ __forceinline__ static void tile_of_yx(int t, int AX, int m1, int& k0, int& o0) {
+    const int tile = (threadIdx.x >> 6) + t * kXyWaves;
+    const int nbx = (m1 + 15) >> 4;
+    const int yb = tile / nbx, xb = tile - yb * nbx;
+    k0 = (AX == 1 ? xb : yb) * 16;
+    o0 = (AX == 1 ? yb : xb) * 16;
+  }
+  // One pass.  YX: tiles in (y block, x block) order; ACC: accumulate onto
+  // r (the other pass's sums of the same elements); fscale multiplies the
+  // filter (the kinetic factor -1/(2 h^2) of the pass's axis).
+  template <int OP, int AX, bool YX = false, bool ACC = false>
+  __device__ __forceinline__ static void conv(V* buf, int m1, int m2, int pitch, Res& r,
+                                              double fscale = 1.0) {
     constexpr int S = Frag<OP>::S, OHI = Frag<OP>::OHI;
     const int lane = threadIdx.x & 63, li = lane & 15, q = lane >> 4;
     const int mc = AX == 1 ? m1 : m2, mo = AX == 1 ? m2 : m1;
@@ -299,14 +335,15 @@ struct MfEngine {
     // hoisted (and kept live in registers) across a loop over orbitals
     asm volatile("" : "+s"(ft));
     #pragma unroll
-    for (int s = 0; s < S; ++s) fc[s] = ft[s * 64 + lane];
-    r.n = 0;
+    for (int s = 0; s < S; ++s) fc[s] = ft[s * 64 + lane] * fscale;
+    if (!ACC) r.n = 0;
     #pragma unroll
     for (int t = 0; t < MT; ++t) {
       if ((threadIdx.x >> 6) + t * kXyWaves >= nt) break;
-      r.n = t + 1;
+      if (!ACC) r.n = t + 1;
       int k0, o0;
-      tile_of(t, nbo, k0, o0);
+      if (YX) tile_of_yx(t, AX, m1, k0, o0);
+      else tile_of(t, nbo, k0, o0);
       const int line = min(o0 + li, mo - 1);      // rows/columns past the end: unused outputs
       const V* lp = AX == 1 ? buf + line * pitch : buf + line;
       // input index of step s: (k0 - OHI + 4 s + q) mod mc; lines are at
@@ -321,6 +358,7 @@ struct MfEngine {
         j = j >= mc ? j - mc : j;
       }
       d4 acc = {0.0, 0.0, 0.0, 0.0};
+      if (ACC) acc = r.r[t];
       #pragma unroll
       for (int s = 0; s < S; ++s)
         acc = AX == 1 ? __builtin_amdgcn_mfma_f64_16x16x4f64(x[s], fc[s], acc, 0, 0, 0)
@@ -367,6 +405,13 @@ struct MfEngine {
                                         const Res& r) {
     each<2>(m1, m2, r, [&](int y, int x, double val) {
       T::st(dst, gp + (int64_t)y * m1 + x, plane, val);
+    });
+  }
+  __device__ __forceinline__ static void add_global_y(void* dst, int64_t gp, int64_t plane, int m1,
+                                                      int m2, const Res& r) {
+    each<2>(m1, m2, r, [&](int y, int x, double val) {
+      const int64_t i = gp + (int64_t)y * m1 + x;
+      T::st(dst, i, plane, T::ldc(dst, i, plane) + val);
     });
   }
 };
@@ -428,28 +473,40 @@ __device__ __forceinline__ void xy_orbital_plane(const XyArgs& a, int b, int z, 
                             [&](int, int pos, V v) { buf[pos] = v; });
   __syncthreads();
   double ek = 0.0;
-  {
+  if constexpr (E::kFusedK) {
+    // K_y c then K_x c accumulated onto it, the axis factors folded into the
+    // filters; one dot for the energy, one store of kxy, c never leaves LDS
     typename E::Res r;
-    E::template conv<OP_CK, 2>(buf, m1, m2, pitch, r);
-    E::scale(r, ks2);
+    E::template conv<OP_CK, 2, true, false>(buf, m1, m2, pitch, r, ks2);
+    E::template conv<OP_CK, 1, true, true>(buf, m1, m2, pitch, r, ks1);
     ek += E::template dot<2>(buf, m1, m2, pitch, r);
     if (a.kin_mul != 1.0) E::scale(r, a.kin_mul);
     E::store_global_y(a.kxy, gp, a.plane, m1, m2, r);
-  }
-  {
-    typename E::Res r;
-    E::template conv<OP_CK, 1>(buf, m1, m2, pitch, r);
-    E::scale(r, ks1);
-    ek += E::template dot<1>(buf, m1, m2, pitch, r);
-    if (a.kin_mul != 1.0) E::scale(r, a.kin_mul);
     __syncthreads();
-    E::template store<1>(buf, m1, m2, pitch, r);
+  } else {
+    {
+      typename E::Res r;
+      E::template conv<OP_CK, 2>(buf, m1, m2, pitch, r);
+      E::scale(r, ks2);
+      ek += E::template dot<2>(buf, m1, m2, pitch, r);
+      if (a.kin_mul != 1.0) E::scale(r, a.kin_mul);
+      E::store_global_y(a.kxy, gp, a.plane, m1, m2, r);
+    }
+    {
+      typename E::Res r;
+      E::template conv<OP_CK, 1>(buf, m1, m2, pitch, r);
+      E::scale(r, ks1);
+      ek += E::template dot<1>(buf, m1, m2, pitch, r);
+      if (a.kin_mul != 1.0) E::scale(r, a.kin_mul);
+      __syncthreads();
+      E::template store<1>(buf, m1, m2, pitch, r);
+    }
+    __syncthreads();
+    plane_batched<kPlaneBatch>(m1, npl, pitch, [&](int e) { return T::ldc(a.kxy, gp + e, a.plane); },
+                              [&](int e, int pos, V ky) {
+                                T::st(a.kxy, gp + e, a.plane, T::plus(ky, buf[pos]));
+                              });
   }
-  __syncthreads();
-  plane_batched<kPlaneBatch>(m1, npl, pitch, [&](int e) { return T::ldc(a.kxy, gp + e, a.plane); },
-                            [&](int e, int pos, V ky) {
-                              T::st(a.kxy, gp + e, a.plane, T::plus(ky, buf[pos]));
-                            });
   // ---- per-(orbital, plane) energies (the block sums end with a barrier)
   const double sp = xy_block_sum(ep);
   const double sk = xy_block_sum(ek);
@@ -489,6 +546,82 @@ void k_xy(XyArgs a) {
     const PassGeom geo{a.orbs, a.pq, a.norb, a.order, a.perm, a.queue, a.ntiles, 0};
     for_each_tile(geo, [&](int b, int z, int) { xy_orbital_plane<P, E, SHARED>(a, b, z, 0, 0); });
   }
+}
+
+// ---------------------------------------------------------------------------
+// In-plane part of the preconditioner's operator (the Helmholtz operator of
+// Sec. 2, Eq. "precon", with the wavelet transforms and the kinetic filter
+// combined, Sec. 6.1): for one (orbital, z-plane) per workgroup,
+//     kq += (K_x + K_y) p        (kq holds K_z p from the z pass)
+// with the plane of p in LDS, both in-plane passes of the combined kinetic
+// filter, and <p, (K_x + K_y) p> per plane for the CG step length.
+// ---------------------------------------------------------------------------
+template <int P, typename E, int WPE>
+__global__ __launch_bounds__(kXyThreads) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
+void k_helm_xy(HelmArgs a) {
+  using T = Prec<P>;
+  using V = typename T::V;
+  extern __shared__ __align__(16) unsigned char xy_lds[];
+  V* buf = reinterpret_cast<V*>(xy_lds);
+  int b, z;
+  find_tile(a.pq, a.norb, blockIdx.x, b, z);
+  const OrbDev od = a.orbs[b];
+  const int m1 = od.m[0], m2 = od.m[1];
+  const int pitch = E::pitch(m1);
+  const int npl = m1 * m2;
+  const int64_t gp = od.off + (int64_t)z * npl;
+  plane_batched<kPlaneBatch>(m1, npl, pitch, [&](int e) { return T::ldc(a.p, gp + e, a.plane); },
+                            [&](int, int pos, V v) { buf[pos] = v; });
+  __syncthreads();
+  double ek = 0.0;
+  if constexpr (E::kFusedK) {
+    typename E::Res r;
+    E::template conv<OP_CK, 2, true, false>(buf, m1, m2, pitch, r, od.kscale[1]);
+    E::template conv<OP_CK, 1, true, true>(buf, m1, m2, pitch, r, od.kscale[0]);
+    ek += E::template dot<2>(buf, m1, m2, pitch, r);
+    E::add_global_y(a.kq, gp, a.plane, m1, m2, r);
+  } else {
+    {
+      typename E::Res r;
+      E::template conv<OP_CK, 2>(buf, m1, m2, pitch, r);
+      E::scale(r, od.kscale[1]);
+      ek += E::template dot<2>(buf, m1, m2, pitch, r);
+      E::add_global_y(a.kq, gp, a.plane, m1, m2, r);
+    }
+    {
+      typename E::Res r;
+      E::template conv<OP_CK, 1>(buf, m1, m2, pitch, r);
+      E::scale(r, od.kscale[0]);
+      ek += E::template dot<1>(buf, m1, m2, pitch, r);
+      __syncthreads();
+      E::template store<1>(buf, m1, m2, pitch, r);
+    }
+    __syncthreads();
+    plane_batched<kPlaneBatch>(m1, npl, pitch, [&](int e) { return T::ldc(a.kq, gp + e, a.plane); },
+                              [&](int e, int pos, V k) {
+                                T::st(a.kq, gp + e, a.plane, T::plus(k, buf[pos]));
+                              });
+  }
+  const double sk = xy_block_sum(ek);
+  if (threadIdx.x == 0) a.ekin[blockIdx.x] = sk;
+}
+
+template <int P, typename E>
+void helm_launch_e(const HelmArgs& a, int nblocks, size_t lds, hipStream_t st) {
+  hipLaunchKernelGGL((k_helm_xy<P, E, 4>), dim3(nblocks), dim3(kXyThreads), lds, st, a);
+}
+
+template <int P>
+void helm_launch_v(const HelmArgs& a, int mi, int nblocks, size_t lds, hipStream_t st) {
+  if (mi <= 3) helm_launch_e<P, VecEngine<P, 3>>(a, nblocks, lds, st);
+  else if (mi <= 5) helm_launch_e<P, VecEngine<P, 5>>(a, nblocks, lds, st);
+  else helm_launch_e<P, VecEngine<P, 8>>(a, nblocks, lds, st);
+}
+
+inline void helm_launch_m(const HelmArgs& a, int mt, int nblocks, size_t lds, hipStream_t st) {
+  if (mt <= 2) helm_launch_e<F64, MfEngine<2>>(a, nblocks, lds, st);
+  else if (mt <= 5) helm_launch_e<F64, MfEngine<5>>(a, nblocks, lds, st);
+  else helm_launch_e<F64, MfEngine<8>>(a, nblocks, lds, st);
 }
 
 template <int P, typename E, bool SH>

@@ -213,14 +213,19 @@ class Plan:
                                 ptr(self.ws), stream_handle())
         return out
 
-    def precondition(self, g, eps, iters, separate=False, out=None, residuals=False):
+    def precondition(self, g, eps, iters, separate=False, out=None, residuals=False, form=None):
         """Preconditioned gradients: `iters` PCG steps on (-1/2 nabla^2 - eps_b) x = g_b
-        for every orbital (eps: one negative value per orbital, host side)."""
+        for every orbital (eps: one negative value per orbital, host side).
+        form: None (default: fused plane kernel when it fits), "passes"
+        (combined filter, one pass per axis) or "separate"."""
+        if form == "separate":
+            separate = True
         out = self.empty() if out is None else out
         e = np.ascontiguousarray(np.broadcast_to(np.asarray(eps, dtype=np.float64), (self.norb,)))
         res = torch.empty(self.norb, dtype=torch.float64, device=self.dev) if residuals else None
         lib.wvl_precondition(self.h, ptr(g), e.ctypes.data_as(lib.DP), int(iters),
-                             lib.WVL_PRECOND_SEPARATE if separate else 0, ptr(out), ptr(res),
+                             lib.WVL_PRECOND_SEPARATE if separate else
+                             (lib.WVL_PRECOND_PASSES if form == "passes" else 0), ptr(out), ptr(res),
                              ptr(self.ws), stream_handle())
         return (out, res) if residuals else out
 

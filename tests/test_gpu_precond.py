@@ -1,8 +1,10 @@
 """GPU parity of the preconditioner (Sec. 2, Eq. "precon"): `iters` steps of
 preconditioned conjugate gradients on (-1/2 nabla^2 - eps_b) x = g_b for every
 orbital, against the float64 oracle running the same steps, in the three
-precisions and in both operator forms (the combined filter per axis, and the
-separate synthesis / kinetic-with-K_0 / analysis passes of Sec. 3.4)."""
+precisions and in the three operator forms (the combined wavelet + kinetic
+filter with both in-plane axes in one plane-resident kernel, the combined
+filter one pass per axis, and the separate synthesis / kinetic-with-K_0 /
+analysis passes of Sec. 3.4)."""
 
 import numpy as np
 import pytest
@@ -26,29 +28,32 @@ def _eps(seed, n):
     return -inputs.rng_for(seed).uniform(0.1, 1.0, size=n)
 
 
+FORMS = [None, "passes", "separate"]
+FORM_IDS = ["plane", "passes", "separate"]
+
+
 @pytest.mark.parametrize("prec", ["f64", "f32", "f32c"])
-@pytest.mark.parametrize("separate", [False, True], ids=["combined", "separate"])
+@pytest.mark.parametrize("form", FORMS, ids=FORM_IDS)
 @pytest.mark.parametrize("case", list(CASES))
-def test_precondition_matches_oracle(case, separate, prec):
+def test_precondition_matches_oracle(case, form, prec):
     norb, dims = CASES[case]
     cs = inputs.random_case(100 + norb, norb, dims)
     eps = _eps(7, norb)
     iters = 4
     plan = ops.Plan(cs["dims"], prec=prec, hgrid=HG)
-    gt, res = plan.precondition(plan.pack(cs["C"]), eps, iters, separate=separate,
-                                residuals=True)
+    gt, res = plan.precondition(plan.pack(cs["C"]), eps, iters, form=form, residuals=True)
     ref = [PC.pcg(g, e, iters, HG) for g, e in zip(cs["C"], eps)]
     assert_close(plan.unpack(gt), [r[0] for r in ref], TOL[prec], "preconditioned gradient")
     assert_close(res.cpu().numpy(), np.array([r[1] for r in ref]), TOL[prec], "residual norms")
 
 
-@pytest.mark.parametrize("separate", [False, True], ids=["combined", "separate"])
-def test_many_steps_float64(separate):
+@pytest.mark.parametrize("form", FORMS, ids=FORM_IDS)
+def test_many_steps_float64(form):
     """60 steps: the iteration stays on the oracle's path to convergence."""
     cs = inputs.random_case(111, 2, (4, 5, 6))
     eps = _eps(8, 2)
     plan = ops.Plan(cs["dims"], prec="f64", hgrid=HG)
-    gt, res = plan.precondition(plan.pack(cs["C"]), eps, 60, separate=separate, residuals=True)
+    gt, res = plan.precondition(plan.pack(cs["C"]), eps, 60, form=form, residuals=True)
     ref = [PC.pcg(g, e, 60, HG) for g, e in zip(cs["C"], eps)]
     assert_close(plan.unpack(gt), [r[0] for r in ref], 1e-11, "60 steps")
     assert np.all(res.cpu().numpy() < 1e-9)
@@ -63,5 +68,18 @@ def test_zero_steps_and_forms_agree():
     assert torch.count_nonzero(x0).item() == 0
     assert_close(r0.cpu().numpy(), np.array([np.linalg.norm(x) for x in cs["C"]]), 1e-14)
     a = plan.precondition(g, eps, 6)
-    b = plan.precondition(g, eps, 6, separate=True)
-    assert_close(plan.unpack(a), plan.unpack(b), 1e-12, "combined vs separate")
+    b = plan.precondition(g, eps, 6, form="separate")
+    c = plan.precondition(g, eps, 6, form="passes")
+    assert_close(plan.unpack(a), plan.unpack(b), 1e-12, "plane vs separate")
+    assert_close(plan.unpack(a), plan.unpack(c), 1e-12, "plane vs passes")
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32c"])
+def test_precondition_uneven_batch(prec):
+    """Orbitals of different grids: the plane kernel sized for the largest."""
+    cs = inputs.random_uneven_case(113, 7, lo=3, hi=18)
+    eps = _eps(10, 7)
+    plan = ops.Plan(cs["dims"], prec=prec, shared_v=False, hgrid=HG)
+    gt = plan.precondition(plan.pack(cs["C"]), eps, 3)
+    ref = [PC.pcg(g, e, 3, HG)[0] for g, e in zip(cs["C"], eps)]
+    assert_close(plan.unpack(gt), ref, TOL[prec], "uneven batch")
