@@ -76,7 +76,8 @@ def stage_model(stage, prec, variant):
 
 # the sources each profiled kernel is built from
 STAGE_SOURCES = {
-    "xy_plane": ["wvl_xy.hip", "wvl_plane.h", "wvl_kernels.h", "wvl_internal.h", "filters_gen.h"],
+    "xy_plane": ["wvl_xy.hip", "wvl_xy_impl.h", "wvl_xy_mf_sh.hip", "wvl_plane.h", "wvl_kernels.h",
+                 "wvl_internal.h", "filters_gen.h"],
 }
 
 
@@ -435,6 +436,8 @@ def main():
     ap.add_argument("--precs", default="f64,f32c,f32")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-uneven", action="store_true")
+    ap.add_argument("--no-precond", action="store_true")
+    ap.add_argument("--no-compressed", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -468,11 +471,13 @@ def main():
                                       not args.no_cpu_baseline)
         torch.cuda.empty_cache()
 
-    print("[bench] compressed orbitals", file=sys.stderr, flush=True)
-    compressed = run_compressed(C, V, dims, args.steps, 2, not args.no_cpu_baseline)
-
-    print("[bench] preconditioner", file=sys.stderr, flush=True)
-    precond = run_precond(C, dims, max(3, args.steps // 4), 1, not args.no_cpu_baseline)
+    compressed = precond = None
+    if not args.no_compressed:
+        print("[bench] compressed orbitals", file=sys.stderr, flush=True)
+        compressed = run_compressed(C, V, dims, args.steps, 2, not args.no_cpu_baseline)
+    if not args.no_precond:
+        print("[bench] preconditioner", file=sys.stderr, flush=True)
+        precond = run_precond(C, dims, max(3, args.steps // 4), 1, not args.no_cpu_baseline)
 
     uneven = None
     if not args.no_uneven:
