@@ -49,9 +49,13 @@ typedef enum {
   WVL_OK = 0,
   WVL_EINVAL = -1,       /* bad argument (null pointer, bad size, aliasing ...) */
   WVL_EUNSUPPORTED = -2, /* valid but not supported by this plan              */
-  WVL_ENOMEM = -3,       /* device allocation failed                           */
+  WVL_ENOMEM = -3,       /* device allocation failed (forced for every device
+                            allocation of the library when the environment
+                            variable WVL_DEBUG_FAIL_ALLOC is 1)               */
   WVL_EHIP = -4,         /* HIP runtime error                                  */
-  WVL_ETIMEOUT = -5,     /* device-side wait exceeded its bound                */
+  WVL_ETIMEOUT = -5,     /* reserved: no call waits on the device (work-queue
+                            kernels take tiles with atomics and never wait for
+                            one another), so none returns it                  */
   WVL_ENODEV = -6        /* no usable GPU (also: dry plans on a host)          */
 } wvl_status;
 

@@ -36,7 +36,8 @@ int fail(int code, const char* fmt, ...) {
 }
 
 int hipfail(hipError_t e, const char* where) {
-  return fail(WVL_EHIP, "%s: %s", where, hipGetErrorString(e));
+  return fail(e == hipErrorOutOfMemory ? WVL_ENOMEM : WVL_EHIP, "%s: %s", where,
+              hipGetErrorString(e));
 }
 
 #define WVL_HIP(call)                                   \
@@ -46,6 +47,18 @@ int hipfail(hipError_t e, const char* where) {
   } while (0)
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Every device allocation of the library goes through here.  With the
+// environment variable WVL_DEBUG_FAIL_ALLOC=1 it fails as an exhausted device
+// would, so that the out-of-memory paths can be exercised.
+hipError_t dev_malloc(void** p, size_t bytes) {
+  const char* f = getenv("WVL_DEBUG_FAIL_ALLOC");
+  if (f && f[0] == '1') {
+    *p = nullptr;
+    return hipErrorOutOfMemory;
+  }
+  return hipMalloc(p, bytes);
+}
 
 }  // namespace
 
@@ -511,9 +524,9 @@ int wvl_plan_create(wvl_ctx* ctx, const wvl_orbital* orbs, int32_t norb, int32_t
   p->ws = off;
   if (!ctx->dry) {
     hipError_t e = hipSetDevice(ctx->device);
-    if (e == hipSuccess) e = hipMalloc((void**)&p->d_orbs, sizeof(OrbDev) * norb);
-    if (e == hipSuccess) e = hipMalloc((void**)&p->d_pz, sizeof(int32_t) * (norb + 1) * 18);
-    if (e == hipSuccess) e = hipMalloc((void**)&p->d_info, sizeof(int) * 4);
+    if (e == hipSuccess) e = dev_malloc((void**)&p->d_orbs, sizeof(OrbDev) * norb);
+    if (e == hipSuccess) e = dev_malloc((void**)&p->d_pz, sizeof(int32_t) * (norb + 1) * 18);
+    if (e == hipSuccess) e = dev_malloc((void**)&p->d_info, sizeof(int) * 4);
     if (e != hipSuccess) {
       wvl_plan_destroy(p);
       return fail(WVL_ENOMEM, "plan allocation failed: %s", hipGetErrorString(e));
@@ -563,8 +576,8 @@ int wvl_plan_create(wvl_ctx* ctx, const wvl_orbital* orbs, int32_t norb, int32_t
     std::vector<int32_t> pb(3 * (size_t)(norb + 1));
     for (int a = 0; a < 3; ++a)
       for (int b = 0; b <= norb; ++b) pb[(size_t)a * (norb + 1) + b] = b * p->bc_tiles[a];
-    hipError_t e = hipMalloc((void**)&p->d_orbs_rs, sizeof(OrbDev) * norb);
-    if (e == hipSuccess) e = hipMalloc((void**)&p->d_pb, sizeof(int32_t) * pb.size());
+    hipError_t e = dev_malloc((void**)&p->d_orbs_rs, sizeof(OrbDev) * norb);
+    if (e == hipSuccess) e = dev_malloc((void**)&p->d_pb, sizeof(int32_t) * pb.size());
     if (e == hipSuccess)
       e = hipMemcpy(p->d_orbs_rs, rs.data(), sizeof(OrbDev) * norb, hipMemcpyHostToDevice);
     if (e == hipSuccess)
@@ -1003,11 +1016,11 @@ int autotune(wvl_plan* p) {
   void *c = nullptr, *out = nullptr, *ws = nullptr, *V = nullptr, *e = nullptr;
   hipStream_t st = nullptr;
   hipEvent_t t0 = nullptr, t1 = nullptr;
-  hipError_t err = hipMalloc(&c, arr);
-  if (err == hipSuccess) err = hipMalloc(&out, arr);
-  if (err == hipSuccess) err = hipMalloc(&ws, p->ws);
-  if (err == hipSuccess) err = hipMalloc(&V, vbytes);
-  if (err == hipSuccess) err = hipMalloc(&e, 4 * sizeof(double));
+  hipError_t err = dev_malloc(&c, arr);
+  if (err == hipSuccess) err = dev_malloc(&out, arr);
+  if (err == hipSuccess) err = dev_malloc(&ws, p->ws);
+  if (err == hipSuccess) err = dev_malloc(&V, vbytes);
+  if (err == hipSuccess) err = dev_malloc(&e, 4 * sizeof(double));
   if (err == hipSuccess) err = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
   if (err == hipSuccess) err = hipEventCreate(&t0);
   if (err == hipSuccess) err = hipEventCreate(&t1);
@@ -1353,7 +1366,7 @@ int wvl_plan_set_regions(wvl_plan* p, const int32_t* seg_c, int32_t nseg_c, cons
     for (int32_t q = seg_f[2 * s]; q < seg_f[2 * s + 1]; ++q) { map_f[q] = (int32_t)k; list_f[k++] = q; }
   if (p->d_map_c) { WVL_HIP(hipFree(p->d_map_c)); p->d_map_c = nullptr; }
   void* d = nullptr;
-  hipError_t e = hipMalloc(&d, sizeof(int32_t) * host.size());
+  hipError_t e = dev_malloc(&d, sizeof(int32_t) * host.size());
   if (e != hipSuccess) return fail(WVL_ENOMEM, "region maps: %s", hipGetErrorString(e));
   e = hipMemcpy(d, host.data(), sizeof(int32_t) * host.size(), hipMemcpyHostToDevice);
   if (e != hipSuccess) { (void)hipFree(d); return hipfail(e, "region upload"); }

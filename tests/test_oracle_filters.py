@@ -236,3 +236,39 @@ def test_kinetic_filter_fourier_integral(F):
         integ = dxi * (f.sum() - 0.5 * (f[0] + f[-1]))
         rl = -integ / math.pi
         assert abs(rl - F["r"][14 + l]) < 2e-6, (l, rl, F["r"][14 + l])
+
+
+# ---------------------------------------------------------------- anchor values
+
+# Values of the least-asymmetric order-16 factor (Daubechies, Ten Lectures on
+# Wavelets, 1992, ch. 6 and 8), of its first moment and of the magic and
+# kinetic filters derived from it, computed separately at 60 digits by another
+# route (roots in z, phase fit of m0 on (0, pi)).  They fix the choice of the
+# spectral factor and of its orientation, which the invariants above leave open
+# between mirror images and other factors with 0 < M1 < 1/2.
+ANCHOR_H = {-7: -0.0033824159510050025955, -6: -0.00054213233180001068935,
+            -5: 0.031695087811525991431, -4: 0.0076074873249766081919,
+            -3: -0.14329423835127266284, -2: -0.061273359067811077843,
+            -1: 0.48135965125905339159, 0: 0.77718575169962802862,
+            1: 0.36444189483617893676, 2: -0.051945838107881800736,
+            3: -0.027219029917103486322, 4: 0.049137179673730286787,
+            5: 0.0038087520138944894631, 6: -0.014952258337062199118,
+            7: -0.00030292051472413308126, 8: 0.0018899503327676891843}
+ANCHOR_M1 = 0.16041800328247180267
+ANCHOR_OMEGA = {0: 0.99404156978340039932, -1: -0.0604895289196983516,
+                1: 0.06126258958312079822, -7: 2.7273449291197965966e-6,
+                8: 8.4334247333529341095e-7}
+ANCHOR_R = {0: -3.5536922899131901941, 1: 2.2191465938911163899,
+            2: -0.61561414655700694963, 13: 2.7080049362631943827e-13}
+
+
+def test_anchor_values(F):
+    for j, v in ANCHOR_H.items():
+        assert abs(F["h"][j - F["lo"]] - v) < 1e-15, j
+    assert abs(F["M"][1] - ANCHOR_M1) < 1e-15
+    for l, v in ANCHOR_OMEGA.items():
+        assert abs(F["omega"][l - F["omega_lo"]] - v) < 1e-15, l
+    for l, v in ANCHOR_R.items():
+        assert abs(F["r"][l - F["r_lo"]] - v) < 1e-14 * max(1.0, abs(v)), l
+        assert abs(F["r"][-l - F["r_lo"]] - v) < 1e-14 * max(1.0, abs(v)), -l
+    assert abs(float(np.sum(F["omega"] ** 2)) - 0.9968193186) < 1e-10
