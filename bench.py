@@ -49,6 +49,12 @@ FLOP_AXIS = 4 * 32 + 59
 FLOP_POINTWISE = 4           # rho += f psi^2, V psi
 
 
+VARIANT_NAMES = {0: "pass-by-pass", 1: "plane-resident (vector FMA)",
+                 2: "plane-resident (float64 matrix cores)",
+                 3: "exact int8 digit products on the matrix cores (plane-resident)"}
+NCAND = 15      # tuner candidates: 5 launch sequences x 3 tile shapes
+
+
 def stage_model(stage, prec, variant):
     """(bound, algorithmic bytes per orbital-gridpoint, algorithmic flop per
     orbital-gridpoint) of one profiled stage.  Bytes: each value the stage
@@ -57,7 +63,7 @@ def stage_model(stage, prec, variant):
     operation count for the axes the stage covers."""
     es = ESIZE[prec]
     if stage == "xy_plane":
-        bound = "mfma" if (prec == "f64" and variant == 2) else "alu"
+        bound = "mfma" if ((prec == "f64" and variant == 2) or variant == 3) else "alu"
         return bound, 4 * es, 2 * FLOP_AXIS + FLOP_POINTWISE
     if stage == "z_final":       # t, c, kxy in; H*psi out
         return "hbm", 4 * es, None
@@ -388,10 +394,10 @@ def run_uneven(steps, warmup):
     torch.cuda.synchronize()
     ms = t0.elapsed_time(t1) / steps
     v = ctypes.c_int32()
-    tm = (ctypes.c_double * 12)()
-    lib.wvl_plan_tuning(plan.h, ctypes.byref(v), tm, 12)
+    tm = (ctypes.c_double * NCAND)()
+    lib.wvl_plan_tuning(plan.h, ctypes.byref(v), tm, NCAND)
     pts = int(sum(np.prod(inputs.fine_shape(d)) for d in dims))
-    seqs = ["pass_by_pass", "plane_occ4", "plane_occ2", "plane_vector_engine"]
+    seqs = ["pass_by_pass", "plane_occ4", "plane_occ2", "plane_vector_engine", "exact_products"]
     shapes = ["default_tiles", "half_axis1_tiles", "persistent_4_per_cu"]
     names = [f"{a}/{b}" for a in seqs for b in shapes]
     best = plan.query(lib.WVL_Q_TUNE_BEST)
@@ -416,13 +422,12 @@ def run_uneven(steps, warmup):
                         "replayed from a hipGraph",
             "orbital_gridpoints": pts, "ms_per_hpsi": ms,
             "orbital_gridpoints_per_s": pts / (ms * 1e-3),
-            "variant": {0: "pass-by-pass", 1: "plane-resident (vector FMA)",
-                        2: "plane-resident (float64 matrix cores)"}[v.value],
+            "variant": VARIANT_NAMES[v.value],
             "persistent_launches": bool(plan.query(lib.WVL_Q_PERSISTENT)),
             "tuner_choice": names[best] if best >= 0 else None,
             "axis1_tile_divisor": plan.query(lib.WVL_Q_XDIV),
             "persistent_workgroups_per_cu": plan.query(lib.WVL_Q_PGRID),
-            "tuner_ms": {names[i]: tm[i] for i in range(12) if tm[i] >= 0},
+            "tuner_ms": {names[i]: tm[i] for i in range(NCAND) if tm[i] >= 0},
             "tuning_s": tune_s,
             "rel_err_vs_oracle": {"orbitals": sample, "normwise": (num / den) ** 0.5,
                                   "elementwise": emax, "tolerance": TOL["f32c"]}}
@@ -555,8 +560,7 @@ def main():
         "cpu_baseline": cpu,
         "precisions": {
             p: {"ms_per_step": v["ms_per_step"],
-                "hpsi_variant": {0: "pass-by-pass", 1: "plane-resident (vector FMA)",
-                                 2: "plane-resident (float64 matrix cores)"}[v["variant"]],
+                "hpsi_variant": VARIANT_NAMES[v["variant"]],
                 "orbital_gridpoints_per_s": pts / (v["ms_per_step"] * 1e-3),
                 "hpsi_ms": v["hpsi_ms"],
                 "hpsi_orbital_gridpoints_per_s": pts / (v["hpsi_ms"] * 1e-3),

@@ -108,6 +108,12 @@ struct wvl_plan {
   int xy_m1 = 0, xy_m2 = 0, xy_G = 1, xy_ngroups = 0, xy_blocks = 0, xy_occ = 4;
   int xy_engine = 0;   // in-plane passes: 0 vector FMA, 1 float64 matrix cores
   bool zfuse = true;   // last two z passes of the plane path fused (not for F32C)
+  // exact-product engine of the compensated form (uniform batches with a
+  // shared potential, lengths multiples of 16, isotropic grid spacing)
+  bool oz_ok = false, use_oz = false;
+  int oz_occ_xy = 2, oz_occ_z = 4;   // waves per SIMD of the plane and final kernels
+  std::vector<int32_t> pxz;          // prefix of xz-planes (m2 per orbital)
+  int32_t* d_pxz = nullptr;
   // persistent launches (WVL_PERSISTENT) of the plane path: work order by
   // decreasing cost per tile, and the number of resident workgroups
   bool persistent = false;
@@ -135,7 +141,7 @@ struct wvl_plan {
   // workspace layout (byte offsets)
   size_t ws = 0, o_A = 0, o_B = 0, o_S = 0, o_D = 0, o_cg = 0, o_ez = 0, o_ey = 0, o_ex = 0, o_pp = 0, o_rv = 0,
          o_rho = 0, o_eorb = 0, o_syrk = 0, o_L = 0, o_Li = 0, o_T = 0, o_rhop = 0, o_epl = 0,
-         o_kpl = 0, o_queue = 0;
+         o_kpl = 0, o_queue = 0, o_ozv = 0, o_oze = 0, o_kpl2 = 0;
   // graph cache
   hipStream_t gstream = nullptr;
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
@@ -190,7 +196,7 @@ static int esize(int prec) { return prec == WVL_F32 ? 4 : 8; }
 constexpr int kBcExtra = 29;   // real-space points added along an isolated axis
 
 constexpr int kQueueCounters = 16;   // work-queue counters per launch sequence
-constexpr int kTuneCands = 12;       // launch candidates of the tuner (4 sequences x 3 shapes)
+constexpr int kTuneCands = 15;       // launch candidates of the tuner (5 sequences x 3 shapes)
 
 static int check_plan(const wvl_plan* p) {
   if (!p) return fail(WVL_EINVAL, "plan is NULL");
@@ -453,6 +459,22 @@ int wvl_plan_create(wvl_ctx* ctx, const wvl_orbital* orbs, int32_t norb, int32_t
       p->xy_blocks = p->pq[norb];
     }
   }
+  // exact-product engine of the compensated form
+  {
+    bool ok = prec == WVL_F32C && p->shared && !p->bc_any && !getenv("WVL_F32C_VECTOR");
+    if (ok) ok = oz_supported(p->orbs[0].m[0], p->orbs[0].m[1], p->orbs[0].m[2]);
+    for (int b = 0; ok && b < norb; ++b) {
+      const double* k = p->orbs[b].kscale;
+      ok = k[0] == k[1] && k[1] == k[2];
+    }
+    p->oz_ok = ok;
+    p->use_oz = ok;
+    if (ok) p->variant = 3;
+    if (const char* o = getenv("WVL_EXACT_OCCUPANCY")) p->oz_occ_xy = atoi(o) == 4 ? 4 : 2;
+    if (const char* o = getenv("WVL_EXACT_OCCUPANCY_Z")) p->oz_occ_z = atoi(o) == 2 ? 2 : 4;
+    p->pxz.assign(norb + 1, 0);
+    for (int b = 0; b < norb; ++b) p->pxz[b + 1] = p->pxz[b] + p->orbs[b].m[1];
+  }
   // persistent work order: z-pass tiles cost ~ m3 (one line per lane),
   // in-plane tiles (one plane) cost ~ m1 m2; largest first, ties by index
   {
@@ -512,7 +534,7 @@ int wvl_plan_create(wvl_ctx* ctx, const wvl_orbital* orbs, int32_t norb, int32_t
     p->o_Li = off; off += align256(sizeof(double) * (size_t)norb * norb);
     p->o_T = off; off += align256(sizeof(double) * (size_t)norb * norb);
   }
-  if (p->xy_ok) {   // the plane path may be chosen later by the tuner
+  if (p->xy_ok || p->oz_ok) {   // the plane path may be chosen later by the tuner
     if (p->shared) {
       p->o_rhop = off;
       off += align256(sizeof(double) * (size_t)p->xy_ngroups * p->M);
@@ -520,12 +542,17 @@ int wvl_plan_create(wvl_ctx* ctx, const wvl_orbital* orbs, int32_t norb, int32_t
     p->o_epl = off; off += align256(sizeof(double) * (size_t)p->pq[norb]);
     p->o_kpl = off; off += align256(sizeof(double) * (size_t)p->pq[norb]);
   }
+  if (p->oz_ok) {   // potential as float pairs, plane exponents, per-xz-plane e_kin
+    p->o_ozv = off; off += align256(sizeof(float) * 2 * (size_t)p->M);
+    p->o_oze = off; off += align256(sizeof(int) * (size_t)p->orbs[0].m[2]);
+    p->o_kpl2 = off; off += align256(sizeof(double) * (size_t)p->pxz[norb]);
+  }
   p->o_queue = off; off += align256(sizeof(int32_t) * kQueueCounters);   // work-queue counters
   p->ws = off;
   if (!ctx->dry) {
     hipError_t e = hipSetDevice(ctx->device);
     if (e == hipSuccess) e = dev_malloc((void**)&p->d_orbs, sizeof(OrbDev) * norb);
-    if (e == hipSuccess) e = dev_malloc((void**)&p->d_pz, sizeof(int32_t) * (norb + 1) * 18);
+    if (e == hipSuccess) e = dev_malloc((void**)&p->d_pz, sizeof(int32_t) * (norb + 1) * 19);
     if (e == hipSuccess) e = dev_malloc((void**)&p->d_info, sizeof(int) * 4);
     if (e != hipSuccess) {
       wvl_plan_destroy(p);
@@ -548,6 +575,7 @@ int wvl_plan_create(wvl_ctx* ctx, const wvl_orbital* orbs, int32_t norb, int32_t
     p->d_perm_p = p->d_order_x2 + (norb + 1);
     p->d_order_p = p->d_perm_p + (norb + 1);
     p->d_pc = p->d_order_p + (norb + 1);
+    p->d_pxz = p->d_pc + (norb + 1);
     std::vector<int32_t> all;
     all.insert(all.end(), p->pz.begin(), p->pz.end());
     all.insert(all.end(), p->py.begin(), p->py.end());
@@ -556,7 +584,7 @@ int wvl_plan_create(wvl_ctx* ctx, const wvl_orbital* orbs, int32_t norb, int32_t
     all.insert(all.end(), p->pq.begin(), p->pq.end());
     for (auto* v : {&p->perm_z, &p->order_z, &p->perm_q, &p->order_q, &p->px2, &p->perm_y,
                     &p->order_y, &p->perm_x, &p->order_x, &p->order_x2, &p->perm_p, &p->order_p,
-                    &p->pc}) {
+                    &p->pc, &p->pxz}) {
       all.insert(all.end(), v->begin(), v->end());
       all.resize(all.size() + (norb + 1 - v->size()), 0);
     }
@@ -835,6 +863,82 @@ int hpsi_bc(wvl_plan* p, hipStream_t st, const void* c, const double* V, double 
   return WVL_OK;
 }
 
+// Local H*psi of the compensated form with exact digit products (wvl_oz.hip):
+// potential as float pairs; u = W_z c; the in-plane kernel (psi, rho, e_pot,
+// t, kxy); the density reduction; Hc = W_z^T t + kin_scale k (K_z c + kxy).
+int hpsi_oz(wvl_plan* p, hipStream_t st, const void* c, const double* V, double pot_scale,
+            double kin_scale, void* hpsi, double* rho, double* e_loc, double* e_kin, double* e_orb,
+            void* ws) {
+  const bool want_e = e_loc || e_kin || e_orb;
+  double* rhop = (double*)wsp(ws, p->o_rhop);
+  double* rv = (double*)wsp(ws, p->o_rv);
+  double* eorb = e_orb ? e_orb : (double*)wsp(ws, p->o_eorb);
+  const OzLds l = oz_lds(p->orbs[0].m[0], p->orbs[0].m[1], p->orbs[0].m[2]);
+  OzArgs a{};
+  a.orbs = p->d_orbs;
+  a.norb = p->norb;
+  a.m1 = p->orbs[0].m[0];
+  a.m2 = p->orbs[0].m[1];
+  a.m3 = p->orbs[0].m[2];
+  a.c = (const float*)c;
+  a.out = (float*)hpsi;
+  a.u = (float*)wsp(ws, p->o_A);
+  a.t = (float*)wsp(ws, p->o_B);
+  a.kxy = (float*)wsp(ws, p->o_S);
+  a.plane = p->elems;
+  float* vhl = (float*)wsp(ws, p->o_ozv);
+  int* vexp = (int*)wsp(ws, p->o_oze);
+  a.vhl = vhl;
+  a.vexp = vexp;
+  a.M = p->M;
+  int pe = 0;
+  if (pot_scale != 0.0) (void)frexp(pot_scale, &pe);   // |pot_scale| <= 2^pe
+  a.pexp = pe;
+  a.ps_hi = (float)pot_scale;
+  a.ps_lo = (float)(pot_scale - (double)a.ps_hi);
+  a.ps_scaled = pot_scale != 1.0;
+  a.km_hi = (float)kin_scale;
+  a.km_lo = (float)(kin_scale - (double)a.km_hi);
+  a.km_scaled = kin_scale != 1.0;
+  a.rho_part = rhop;
+  a.ngroups = p->xy_ngroups;
+  a.G = p->xy_G;
+  a.epot = (double*)wsp(ws, p->o_epl);
+  a.pq = p->d_pq;
+  a.ekin = (double*)wsp(ws, p->o_kpl2);
+  a.dxy = l.dxy;
+  a.dz = l.dz;
+  {
+    Mark mk(p, st, ST_POT);
+    WVL_CHK(launch_oz_vprep(V, a.m1 * a.m2, a.m3, vhl, p->M, vexp, st));
+  }
+  {
+    Mark mk(p, st, stage_of(OP_CW, 3));
+    WVL_CHK(launch_oz_z(a, st));
+  }
+  {
+    Mark mk(p, st, ST_XY);
+    WVL_CHK(launch_oz_xy(a, p->oz_occ_xy, st));
+  }
+  if (rho || want_e) {
+    Mark mk(p, st, ST_RHO);
+    WVL_CHK(launch_rho_reduce(rhop, p->xy_ngroups, p->M, V, rho, want_e ? rv : nullptr, st));
+  }
+  {
+    Mark mk(p, st, ST_ZFIN);
+    WVL_CHK(launch_oz_zfinal(a, p->oz_occ_z, st));
+  }
+  if (want_e) {
+    Mark mk(p, st, ST_ENERGY);
+    // kinetic: per xz-plane sums; potential: per z-plane sums
+    WVL_CHK(launch_orb_sums(p->d_orbs, p->norb, p->d_pxz, nullptr, nullptr, a.ekin, nullptr,
+                            nullptr, a.epot, 1, p->d_pq, 0, eorb, st));
+    if (e_loc || e_kin)
+      WVL_CHK(launch_totals(p->d_orbs, p->norb, eorb, rv, p->nblk, e_loc, e_kin, st));
+  }
+  return WVL_OK;
+}
+
 // The local H*psi launch sequence (Sec. 2.4 steps 2-6 with the density of
 // Sec. 2.5 and the float64 energies).  hpsi may be c itself: then the last z
 // step runs as two passes (the fused one would overwrite c at the start of a
@@ -844,6 +948,8 @@ int hpsi_sequence(wvl_plan* p, hipStream_t st, const void* c, const double* V, d
                   double* e_orb, void* ws) {
   if (p->bc_any)
     return hpsi_bc(p, st, c, V, pot_scale, kin_scale, hpsi, rho, e_loc, e_kin, e_orb, ws);
+  if (p->use_oz)
+    return hpsi_oz(p, st, c, V, pot_scale, kin_scale, hpsi, rho, e_loc, e_kin, e_orb, ws);
   Seq q(p, st);
   void* A = wsp(ws, p->o_A);
   void* B = wsp(ws, p->o_B);
@@ -991,25 +1097,27 @@ int hpsi_sequence(wvl_plan* p, hipStream_t st, const void* c, const double* V, d
 //            sequences have no axis-1 pass);
 //   shape 2: persistent launches of 4 workgroups per CU (persistent plans).
 // Unavailable candidates get -1.  The fastest one is kept.
-struct Cand { bool xy; int occ, engine, xdiv, pmul; };
+struct Cand { bool xy; int occ, engine, xdiv, pmul; bool oz; };
 
 void apply_cand(wvl_plan* p, const Cand& c) {
+  p->use_oz = c.oz;
   p->use_xy = c.xy;
   p->xy_occ = c.occ;
   p->xy_engine = c.engine;
   p->xdiv = c.xdiv;
   p->pgrid_mul = c.pmul;
   p->pgrid_pass = std::max(1, p->ctx->cus) * c.pmul;
-  p->variant = c.xy ? 1 + c.engine : 0;
+  p->variant = c.oz ? 3 : c.xy ? 1 + c.engine : 0;
 }
 
 int autotune(wvl_plan* p) {
   const bool mx = xy_matrix_engine(p->prec, p->xy_m1, p->xy_m2);
   const bool plane_ok = xy_supported(p->prec, p->xy_m1, p->xy_m2, mx) && !getenv("WVL_NO_PLANE_KERNEL");
   const bool vec_ok = xy_supported(p->prec, p->xy_m1, p->xy_m2, false) && !getenv("WVL_NO_PLANE_KERNEL");
-  const Cand seqs[4] = {{false, 4, 0, 1, 8}, {true, 4, mx ? 1 : 0, 1, 8}, {true, 2, mx ? 1 : 0, 1, 8},
-                        {true, 4, 0, 1, 8}};
-  const bool seq_ok[4] = {true, plane_ok, plane_ok, mx && vec_ok};
+  const Cand seqs[5] = {{false, 4, 0, 1, 8, false}, {true, 4, mx ? 1 : 0, 1, 8, false},
+                        {true, 2, mx ? 1 : 0, 1, 8, false}, {true, 4, 0, 1, 8, false},
+                        {false, 4, 0, 1, 8, true}};
+  const bool seq_ok[5] = {true, plane_ok, plane_ok, mx && vec_ok, p->oz_ok};
   const size_t es = p->prec == WVL_F32 ? 4 : 8;
   const size_t arr = (size_t)p->elems * (p->prec == WVL_F32C ? 8 : es);
   const size_t vbytes = sizeof(double) * (size_t)(p->shared ? p->Mrs : std::max<int64_t>(p->vlen, 1));
@@ -1028,7 +1136,7 @@ int autotune(wvl_plan* p) {
   if (err == hipSuccess) err = hipMemsetAsync(V, 0, vbytes, st);
   int status = WVL_OK;
   if (err != hipSuccess) status = hipfail(err, "autotune buffers");
-  const Cand keep{p->use_xy, p->xy_occ, p->xy_engine, p->xdiv, p->pgrid_mul};
+  const Cand keep{p->use_xy, p->xy_occ, p->xy_engine, p->xdiv, p->pgrid_mul, p->use_oz};
   int best = -1;
   double best_ms = 0.0;
   p->tune_ms.assign(kTuneCands, -1.0);
@@ -1036,7 +1144,7 @@ int autotune(wvl_plan* p) {
     const int seq = k / 3, shape = k % 3;
     if (!seq_ok[seq]) continue;
     if (shape == 1 && seq != 0) continue;
-    if (shape == 2 && !p->persistent) continue;
+    if (shape == 2 && (!p->persistent || seq == 4)) continue;
     Cand cd = seqs[seq];
     if (shape == 1) cd.xdiv = 2;
     if (shape == 2) cd.pmul = 4;

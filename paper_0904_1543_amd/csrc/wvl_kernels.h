@@ -181,6 +181,40 @@ hipError_t launch_helm_xy(int prec, const HelmArgs& a, int m1, int m2, int nbloc
 
 // engine: the float64 matrix-core form of the in-plane passes
 bool xy_matrix_engine(int prec, int m1, int m2);
+// Exact-product engine of the compensated form (wvl_oz.hip): uniform batches
+// with a shared potential, fine lengths multiples of 16.  Float pairs: hi
+// plane then lo plane, `plane` floats apart.
+struct OzArgs {
+  const OrbDev* orbs;
+  int32_t norb, m1, m2, m3;
+  const float* c;
+  float* out;
+  float* t;
+  float* u;
+  float* kxy;
+  int64_t plane;
+  const float* vhl;      // the potential as float pairs (hi, then lo M floats later)
+  const int* vexp;       // per z-plane exponent of max |V|
+  int64_t M;
+  int32_t pexp;          // |pot_scale| <= 2^pexp
+  float ps_hi, ps_lo, km_hi, km_lo;   // pot_scale and kin_scale as float pairs
+  int32_t ps_scaled, km_scaled;       // != 1
+  double* rho_part;      // [ngroups][M] group partials
+  int32_t ngroups, G;
+  double* epot;          // per (orbital, z-plane) at pq[b] + z
+  const int32_t* pq;
+  double* ekin;          // per (orbital, y) at b * m2 + y: <c, k (K_x + K_y + K_z) c>
+  int32_t dxy, dz;       // digit-plane strides (bytes) of the xy and xz kernels
+};
+struct OzLds { int dxy, dz; size_t xy_bytes, z_bytes; };
+OzLds oz_lds(int m1, int m2, int m3);
+bool oz_supported(int m1, int m2, int m3);
+hipError_t launch_oz_vprep(const double* V, int npl, int m3, float* vhl, int64_t M, int* vexp,
+                           hipStream_t st);
+hipError_t launch_oz_z(const OzArgs& a, hipStream_t st);
+hipError_t launch_oz_xy(const OzArgs& a, int occ, hipStream_t st);
+hipError_t launch_oz_zfinal(const OzArgs& a, int occ, hipStream_t st);
+
 size_t xy_lds_bytes(int prec, int m1, int m2, bool engine);
 bool xy_supported(int prec, int m1, int m2, bool engine);
 // m1, m2: the plane of every orbital of the launch (the largest one for uneven

@@ -1,0 +1,329 @@
+// Local H*psi of the compensated single-precision form with exact digit
+// products on the int8 matrix cores (the engine of wvl_oz.h), for uniform
+// batches with a shared potential and line lengths that are multiples of 16.
+//
+// Three kernels, one plane per workgroup and step, the plane's digits in LDS:
+//   z:      u = W_z c                         over (orbital, y) xz-planes
+//   planes: psi = W_y W_x u, rho, e_pot, y = pot_scale V psi,
+//           t = W_y^T W_x^T y, kxy = (K_x + K_y) c   over z-planes, the
+//           orbitals of a density group in turn (the group's partial in
+//           orbital order, as in the other in-plane kernels)
+//   final:  Hc = W_z^T t + kin_scale k (K_z c + kxy), e_kin   over xz-planes
+// with W = CW, W^T = CWT, K = CK the combined filters (Sec. 2.4, last
+// paragraph; Sec. 3.1 for the separable form) and k = -1/(2 h^2).  t, u and
+// kxy are float pairs in the workspace; every plane enters a kernel as float
+// pairs, is split into digits with its own exponent, and leaves as float
+// pairs (t, u, kxy, Hc) or float64 sums (rho, energies).
+#include <algorithm>
+
+#include "wvl_oz.h"
+
+namespace wvl {
+
+namespace {
+
+constexpr int kOzZWaves = 8;     // z kernels: 512 threads, two workgroups per CU
+constexpr int kOzXyWaves = 12;   // in-plane kernel: 768 threads, 3 tiles per wave at 96 x 96
+
+__device__ __forceinline__ double oz_pair_d(f2 v) { return (double)v.hi + (double)v.lo; }
+
+// ---------------------------------------------------------------------------
+// the potential as float pairs, and the exponent of every z-plane's max |V|
+__global__ __launch_bounds__(256) void k_oz_vprep(const double* V, int npl, float* vhl, int64_t M,
+                                                  int* vexp) {
+  const int z = blockIdx.x;
+  float m = 0.0f;
+  for (int i = threadIdx.x; i < npl; i += 256) {
+    const int64_t e = (int64_t)z * npl + i;
+    const double v = V[e];
+    const float h = (float)v;
+    vhl[e] = h;
+    vhl[M + e] = (float)(v - (double)h);
+    m = fmaxf(m, fabsf(h));
+  }
+  __shared__ float red[4];
+  #pragma unroll
+  for (int s = 32; s > 0; s >>= 1) m = fmaxf(m, __shfl_xor(m, s, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) vexp[z] = oz_exp_of(fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3])));
+}
+
+// ---------------------------------------------------------------------------
+// z step: u = W_z c over the xz-plane (b, y): lines x, contracted z
+__global__ __launch_bounds__(64 * kOzZWaves) __attribute__((amdgpu_waves_per_eu(4, 4)))
+void k_oz_z(OzArgs a) {
+  extern __shared__ __align__(16) uint8_t oz_lds[];
+  const int b = blockIdx.x / a.m2, y = blockIdx.x - b * a.m2;
+  const int m1 = a.m1, m3 = a.m3;
+  const int64_t zs = (int64_t)m1 * a.m2;
+  const int64_t gp = a.orbs[b].off + (int64_t)y * m1;
+  const OzGeo gz{m3, m1, oz_pitch(m3), a.dz};
+  const int e = oz_load<false, kOzZWaves>(a.c, a.plane, gp, zs, gz, oz_lds, -2000);
+  __syncthreads();
+  const int E = e + OzK<OP_CW>::EF - 54;
+  const int lane = threadIdx.x & 63, n = lane & 15, gq = lane >> 4;
+  float* u = a.u;
+  oz_pass<OP_CW, true, kOzZWaves>(oz_lds, gz, 0, [&](int, int k0, int o0, const int64_t (&T)[4]) {
+    // elements (x = o0 + 4 g + v, z = k0 + n)
+    const int64_t at = gp + (int64_t)(k0 + n) * zs + o0 + 4 * gq;
+    float4 h, l;
+    f2 r = oz_tof(T[0], E); h.x = r.hi; l.x = r.lo;
+    r = oz_tof(T[1], E); h.y = r.hi; l.y = r.lo;
+    r = oz_tof(T[2], E); h.z = r.hi; l.z = r.lo;
+    r = oz_tof(T[3], E); h.w = r.hi; l.w = r.lo;
+    *reinterpret_cast<float4*>(u + at) = h;
+    *reinterpret_cast<float4*>(u + a.plane + at) = l;
+  });
+}
+
+// ---------------------------------------------------------------------------
+// planes
+// one (orbital, z-plane); the group's density plane accumulates in LDS
+// (rho_l; bi == 0: first orbital of the group)
+__device__ __forceinline__ void oz_xy_plane(const OzArgs& a, int b, int z, int bi, uint8_t* lds,
+                                            double* rho_l) {
+  constexpr int NW = kOzXyWaves;
+  const int m1 = a.m1, m2 = a.m2;
+  const int npl = m1 * m2;
+  const OzGeo gx{m1, m2, oz_pitch(m1), a.dxy};    // [y][x]: lines y, contracted x
+  const OzGeo gy{m2, m1, oz_pitch(m2), a.dxy};    // [x][y]: lines x, contracted y
+  const OrbDev& od = a.orbs[b];
+  const int64_t gp = od.off + (int64_t)z * npl;
+  const int lane = threadIdx.x & 63, n = lane & 15, gq = lane >> 4;
+
+  // ---- psi = W_y W_x u
+  int e = oz_load<true, NW>(a.u, a.plane, gp, m1, gx, lds, -2000);
+  __syncthreads();
+  oz_pass_to_digits<OP_CW, NW>(lds, gx, gy);
+  e += OzK<OP_CW>::GF;
+  // ---- the y pass gives psi; pointwise: rho (group partial), e_pot and the
+  //      digits of y = pot_scale V psi (exponent ey)
+  const int Epsi = e + OzK<OP_CW>::EF - 54;
+  const int ey = e + OzK<OP_CW>::GF + a.vexp[z] + a.pexp;
+  const float* vh = a.vhl + (int64_t)z * npl;
+  const float* vl = vh + a.M;
+  const double occ = od.occ;
+  const f2 ps{a.ps_hi, a.ps_lo};
+  double ep = 0.0;
+  {
+    OzPacked<NW> pk;
+    pk.n = 0;
+    oz_pass<OP_CW, true, NW>(lds, gy, 0, [&](int t, int k0, int o0, const int64_t (&T)[4]) {
+      // elements (x = o0 + 4 g + v, y = k0 + n): four consecutive x of row y
+      const int pe = (k0 + n) * m1 + o0 + 4 * gq;
+      const float4 h4 = *reinterpret_cast<const float4*>(vh + pe);
+      const float4 l4 = *reinterpret_cast<const float4*>(vl + pe);
+      const float hv[4] = {h4.x, h4.y, h4.z, h4.w}, lv[4] = {l4.x, l4.y, l4.z, l4.w};
+      double r4[4] = {0.0, 0.0, 0.0, 0.0};
+      if (bi != 0) {
+        const double4 q = *reinterpret_cast<const double4*>(rho_l + pe);
+        r4[0] = q.x; r4[1] = q.y; r4[2] = q.z; r4[3] = q.w;
+      }
+      OzZ zz[4];
+      #pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const double pd = oz_tod(T[v], Epsi);
+        const double p2 = pd * pd;
+        r4[v] = __builtin_fma(occ, p2, r4[v]);
+        ep = __builtin_fma((double)hv[v] + (double)lv[v], p2, ep);
+        f2 yv = oz_mul(f2{hv[v], lv[v]}, oz_tof(T[v], Epsi));
+        if (a.ps_scaled) yv = oz_mul(yv, ps);
+        zz[v] = oz_digits(oz_fix(yv.hi, yv.lo, 47 - ey));
+      }
+      *reinterpret_cast<double4*>(rho_l + pe) = make_double4(r4[0], r4[1], r4[2], r4[3]);
+      oz_pack(zz, pk.d[t]);
+      pk.n = t + 1;
+    });
+    __syncthreads();
+    oz_store_packed<NW>(pk, gy, 0, lds, gx);   // y in [y][x]: line y = k0 + n, index x
+    __syncthreads();
+  }
+  e = ey;
+  // ---- t = W_y^T W_x^T y
+  oz_pass_to_digits<OP_CWT, NW>(lds, gx, gy);
+  e += OzK<OP_CWT>::GF;
+  {
+    const int Et = e + OzK<OP_CWT>::EF - 54;
+    float* tp = a.t;
+    oz_pass<OP_CWT, true, NW>(lds, gy, 0, [&](int, int k0, int o0, const int64_t (&T)[4]) {
+      const int64_t at = gp + (int64_t)(k0 + n) * m1 + o0 + 4 * gq;
+      float4 h, l;
+      f2 r = oz_tof(T[0], Et); h.x = r.hi; l.x = r.lo;
+      r = oz_tof(T[1], Et); h.y = r.hi; l.y = r.lo;
+      r = oz_tof(T[2], Et); h.z = r.hi; l.z = r.lo;
+      r = oz_tof(T[3], Et); h.w = r.hi; l.w = r.lo;
+      *reinterpret_cast<float4*>(tp + at) = h;
+      *reinterpret_cast<float4*>(tp + a.plane + at) = l;
+    });
+    __syncthreads();
+  }
+  // ---- kxy = (K_x + K_y) c (without the factor -1/(2 h^2)): the x pass on c
+  //      in [y][x], its sums kept; the y pass on c in [x][y] (data as the B
+  //      operand, so that a lane holds the same elements), the two added
+  //      exactly
+  const int ec = oz_load<true, NW>(a.c, a.plane, gp, m1, gx, lds, -2000);
+  __syncthreads();
+  int64_t Tx[oz_mt(NW)][4];
+  oz_pass<OP_CK, true, NW>(lds, gx, 1, [&](int t, int, int, const int64_t (&T)[4]) {
+    #pragma unroll
+    for (int v = 0; v < 4; ++v) Tx[t][v] = T[v];
+  });
+  __syncthreads();
+  oz_load<false, NW>(a.c, a.plane, gp, m1, gy, lds, ec);
+  __syncthreads();
+  {
+    const int Ek = ec + OzK<OP_CK>::EF - 54;
+    float* kp = a.kxy;
+    oz_pass<OP_CK, false, NW>(lds, gy, 2, [&](int t, int k0, int o0, const int64_t (&T)[4]) {
+      // elements (y = k0 + 4 g + v, x = o0 + n)
+      #pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const f2 r = oz_tof(T[v] + Tx[t][v], Ek);
+        const int64_t at = gp + (int64_t)(k0 + 4 * gq + v) * m1 + o0 + n;
+        kp[at] = r.hi;
+        kp[a.plane + at] = r.lo;
+      }
+    });
+  }
+  const double sp = oz_block_sum<NW>(ep);
+  if (threadIdx.x == 0) a.epot[a.pq[b] + z] = sp;
+}
+
+template <int WPE>
+__global__ __launch_bounds__(64 * kOzXyWaves) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
+void k_oz_xy(OzArgs a) {
+  extern __shared__ __align__(16) uint8_t oz_lds[];
+  double* rho_l = reinterpret_cast<double*>(oz_lds + kOzDig * a.dxy);
+  const int g = blockIdx.x % a.ngroups;
+  const int z = blockIdx.x / a.ngroups;
+  #pragma nounroll
+  for (int slot = 0; slot < a.G; ++slot) {
+    const int b = g * a.G + slot;
+    if (b >= a.norb) break;
+    oz_xy_plane(a, b, z, slot, oz_lds, rho_l);
+  }
+  // the group's density partial of this plane, once
+  __syncthreads();
+  const int npl = a.m1 * a.m2;
+  double* rp = a.rho_part + (int64_t)g * a.M + (int64_t)z * npl;
+  for (int e = 2 * threadIdx.x; e < npl; e += 2 * 64 * kOzXyWaves)
+    *reinterpret_cast<double2*>(rp + e) = *reinterpret_cast<const double2*>(rho_l + e);
+}
+
+// ---------------------------------------------------------------------------
+// final z step over the xz-plane (b, y):
+//   Hc = W_z^T t + kin_scale k (K_z c + kxy),  e_kin = <c, k (K_z c + kxy)>
+template <int WPE>
+__global__ __launch_bounds__(64 * kOzZWaves) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
+void k_oz_zfinal(OzArgs a) {
+  extern __shared__ __align__(16) uint8_t oz_lds[];
+  const int b = blockIdx.x / a.m2, y = blockIdx.x - b * a.m2;
+  const int m1 = a.m1, m3 = a.m3;
+  const int64_t zs = (int64_t)m1 * a.m2;
+  const OrbDev& od = a.orbs[b];
+  const int64_t gp = od.off + (int64_t)y * m1;
+  const OzGeo gz{m3, m1, oz_pitch(m3), a.dz};
+  const int lane = threadIdx.x & 63, n = lane & 15, gq = lane >> 4;
+  constexpr int NW = kOzZWaves;
+  const int et = oz_load<false, NW>(a.t, a.plane, gp, zs, gz, oz_lds, -2000);
+  __syncthreads();
+  int64_t Tt[oz_mt(NW)][4];
+  oz_pass<OP_CWT, true, NW>(oz_lds, gz, 0, [&](int t, int, int, const int64_t (&T)[4]) {
+    #pragma unroll
+    for (int v = 0; v < 4; ++v) Tt[t][v] = T[v];
+  });
+  __syncthreads();
+  const int ec = oz_load<false, NW>(a.c, a.plane, gp, zs, gz, oz_lds, -2000);
+  __syncthreads();
+  const int Et = et + OzK<OP_CWT>::EF - 54;
+  const int Ek = ec + OzK<OP_CK>::EF - 54;
+  // k = -1/(2 h^2) of this orbital (the same along every axis) as a float pair
+  const double kd = od.kscale[0];
+  const float kh = (float)kd;
+  const f2 ks{kh, (float)(kd - (double)kh)};
+  const f2 km{a.km_hi, a.km_lo};
+  double ek = 0.0;
+  const float* kxy = a.kxy;
+  const float* c = a.c;
+  float* out = a.out;
+  oz_pass<OP_CK, true, NW>(oz_lds, gz, 0, [&](int t, int k0, int o0, const int64_t (&T)[4]) {
+    // elements (x = o0 + 4 g + v, z = k0 + n)
+    const int64_t at = gp + (int64_t)(k0 + n) * zs + o0 + 4 * gq;
+    const float4 kh4 = *reinterpret_cast<const float4*>(kxy + at);
+    const float4 kl4 = *reinterpret_cast<const float4*>(kxy + a.plane + at);
+    const float4 ch4 = *reinterpret_cast<const float4*>(c + at);
+    const float4 cl4 = *reinterpret_cast<const float4*>(c + a.plane + at);
+    const float khv[4] = {kh4.x, kh4.y, kh4.z, kh4.w}, klv[4] = {kl4.x, kl4.y, kl4.z, kl4.w};
+    const float chv[4] = {ch4.x, ch4.y, ch4.z, ch4.w}, clv[4] = {cl4.x, cl4.y, cl4.z, cl4.w};
+    float oh[4], ol[4];
+    #pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const f2 kc = oz_mul(oz_add(oz_tof(T[v], Ek), f2{khv[v], klv[v]}), ks);
+      ek = __builtin_fma((double)chv[v] + (double)clv[v], oz_pair_d(kc), ek);
+      const f2 o = oz_add(oz_tof(Tt[t][v], Et), a.km_scaled ? oz_mul(kc, km) : kc);
+      oh[v] = o.hi;
+      ol[v] = o.lo;
+    }
+    *reinterpret_cast<float4*>(out + at) = make_float4(oh[0], oh[1], oh[2], oh[3]);
+    *reinterpret_cast<float4*>(out + a.plane + at) = make_float4(ol[0], ol[1], ol[2], ol[3]);
+  });
+  const double sk = oz_block_sum<NW>(ek);
+  if (threadIdx.x == 0) a.ekin[(int64_t)b * a.m2 + y] = sk;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// host side
+
+OzLds oz_lds(int m1, int m2, int m3) {
+  OzLds r;
+  const int axy = std::max(m2 * oz_pitch(m1), m1 * oz_pitch(m2));
+  r.dxy = (axy + 15) & ~15;
+  r.dz = (m1 * oz_pitch(m3) + 15) & ~15;
+  r.xy_bytes = (size_t)kOzDig * r.dxy + sizeof(double) * (size_t)m1 * m2;   // digits + rho plane
+  r.z_bytes = (size_t)kOzDig * r.dz;
+  return r;
+}
+
+bool oz_supported(int m1, int m2, int m3) {
+  for (int m : {m1, m2, m3})
+    if (m < 16 || (m & 15) != 0) return false;
+  // tiles per wave and pass, value quads per thread when loading a plane
+  const int txy = (m1 >> 4) * (m2 >> 4), txz = (m1 >> 4) * (m3 >> 4);
+  if (txy > kOzMaxTiles || txz > kOzMaxTiles) return false;
+  if (m1 * m2 / 4 > kOzMaxQuads || m1 * m3 / 4 > kOzMaxQuads) return false;
+  const OzLds l = oz_lds(m1, m2, m3);
+  return l.xy_bytes <= 160 * 1024 && l.z_bytes <= 160 * 1024;
+}
+
+hipError_t launch_oz_vprep(const double* V, int npl, int m3, float* vhl, int64_t M, int* vexp,
+                           hipStream_t st) {
+  hipLaunchKernelGGL(k_oz_vprep, dim3(m3), dim3(256), 0, st, V, npl, vhl, M, vexp);
+  return hipGetLastError();
+}
+
+hipError_t launch_oz_z(const OzArgs& a, hipStream_t st) {
+  const OzLds l = oz_lds(a.m1, a.m2, a.m3);
+  hipLaunchKernelGGL(k_oz_z, dim3(a.norb * a.m2), dim3(64 * kOzZWaves), l.z_bytes, st, a);
+  return hipGetLastError();
+}
+
+// one workgroup of 12 waves per CU (3 waves per SIMD)
+hipError_t launch_oz_xy(const OzArgs& a, int occ, hipStream_t st) {
+  const OzLds l = oz_lds(a.m1, a.m2, a.m3);
+  (void)occ;
+  hipLaunchKernelGGL(k_oz_xy<3>, dim3(a.m3 * a.ngroups), dim3(64 * kOzXyWaves), l.xy_bytes, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_oz_zfinal(const OzArgs& a, int occ, hipStream_t st) {
+  const OzLds l = oz_lds(a.m1, a.m2, a.m3);
+  const dim3 g(a.norb * a.m2), b(64 * kOzZWaves);
+  if (occ == 4) hipLaunchKernelGGL(k_oz_zfinal<4>, g, b, l.z_bytes, st, a);
+  else hipLaunchKernelGGL(k_oz_zfinal<2>, g, b, l.z_bytes, st, a);
+  return hipGetLastError();
+}
+
+}  // namespace wvl

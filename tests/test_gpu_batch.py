@@ -23,7 +23,7 @@ pytestmark = pytest.mark.gpu
 TOL = {"f64": 1e-12, "f32": 2e-6, "f32c": 1e-10}
 
 
-NCAND = 12   # tuner candidates: 4 launch sequences x 3 tile shapes
+NCAND = 15   # tuner candidates: 5 launch sequences x 3 tile shapes
 
 
 def _tuning(plan):

@@ -1,0 +1,136 @@
+"""The compensated form's exact-product engine (int8 digit products on the
+matrix cores, float pairs in memory) against the float64 oracle.
+
+The engine runs the local H*psi of uniform batches with a shared potential,
+fine lengths that are multiples of 16 and the same grid spacing along every
+axis (variant 3, asserted).  Cases: one 16 x 16 tile per plane (the 64-input
+window wraps four times), non-cubic planes of several tiles, density groups
+G > 1 with a ragged last group, anisotropic spacing (falls back to the vector
+engine), the two scale factors, in place, an all-zero orbital and orbitals
+scaled by 1e-20 and 1e15 (each plane takes its own exponent).  Every result
+is held to 1e-10 normwise and elementwise (Sec. 2.4 steps 2-6, Sec. 2.5).
+"""
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import wavelet as W
+from paper_0904_1543_amd import inputs, lib, ops
+from parity_helpers import assert_close, assert_scalar
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+# (orbitals, coarse dims) -> fine (2 n3, 2 n2, 2 n1)
+CASES = {"one_tile": (2, (8, 8, 8)), "nonsquare": (3, (16, 24, 8)),
+         "tall": (2, (24, 16, 32)), "groups": (67, (8, 8, 16))}
+
+
+def _check(plan, cs, r, ref, hg=(1.0, 1.0, 1.0), what=""):
+    assert_close(plan.unpack(r["hpsi"]), list(ref["hpsi"]), TOL, what + "hpsi")
+    assert_close(r["rho"].cpu().numpy(), ref["rho"].ravel(), TOL, what + "rho")
+    e = r["energies"].cpu().numpy()
+    assert_scalar(e[0], ref["e_loc"], TOL, what + "E_loc")
+    assert_scalar(e[1], ref["e_kin"], TOL, what + "E_kin")
+    eo = r["e_orb"].cpu().numpy()
+    assert_close(eo[: plan.norb], ref["e_loc_orb"], TOL, what + "e_pot per orbital")
+    assert_close(eo[plan.norb:], ref["e_kin_orb"], TOL, what + "e_kin per orbital")
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_exact_engine_against_oracle(case):
+    norb, dims = CASES[case]
+    cs = inputs.random_case(150 + norb, norb, dims, potential="gauss16")
+    plan = ops.Plan(cs["dims"], prec="f32c")
+    assert plan.query(lib.WVL_Q_VARIANT) == 3
+    if case == "groups":
+        assert plan.query(lib.WVL_Q_GROUP) == 2
+    ref = W.local_hpsi(cs["C"], cs["V"], cs["occ"])
+    r = plan.local_hpsi(plan.pack(cs["C"]), plan.pack_potential(cs["V"]), per_orbital=True)
+    _check(plan, cs, r, ref)
+
+
+@pytest.mark.parametrize("occ_xy", ["2", "4"])
+def test_exact_engine_both_occupancies(occ_xy, monkeypatch):
+    monkeypatch.setenv("WVL_EXACT_OCCUPANCY", occ_xy)
+    cs = inputs.random_case(160, 3, (16, 24, 8), potential="gauss16")
+    plan = ops.Plan(cs["dims"], prec="f32c")
+    ref = W.local_hpsi(cs["C"], cs["V"], cs["occ"])
+    r = plan.local_hpsi(plan.pack(cs["C"]), plan.pack_potential(cs["V"]), per_orbital=True)
+    _check(plan, cs, r, ref)
+
+
+def test_isotropic_spacing_and_anisotropic_fallback():
+    cs = inputs.random_case(161, 2, (16, 8, 16), potential="gauss16")
+    for hg, variant in [((0.8, 0.8, 0.8), 3), ((0.8, 1.0, 0.9), 1)]:
+        plan = ops.Plan(cs["dims"], prec="f32c", hgrid=hg)
+        assert plan.query(lib.WVL_Q_VARIANT) == variant
+        ref = W.local_hpsi(cs["C"], cs["V"], cs["occ"], hgrid=hg)
+        r = plan.local_hpsi(plan.pack(cs["C"]), plan.pack_potential(cs["V"]), per_orbital=True)
+        _check(plan, cs, r, ref, hg, f"h={hg}: ")
+
+
+@pytest.mark.parametrize("scales", [(0.7, -1.3), (0.0, 1.0), (2.5, 0.0)])
+def test_exact_engine_scales(scales):
+    ps, ks = scales
+    cs = inputs.random_case(162, 3, (16, 8, 16), potential="gauss16")
+    plan = ops.Plan(cs["dims"], prec="f32c")
+    full = W.local_hpsi(cs["C"], cs["V"], cs["occ"])
+    kin = W.local_hpsi(cs["C"], np.zeros_like(cs["V"]), cs["occ"])
+    want = [ps * (h - k) + ks * k for h, k in zip(full["hpsi"], kin["hpsi"])]
+    r = plan.local_hpsi(plan.pack(cs["C"]), plan.pack_potential(cs["V"]), pot_scale=ps,
+                        kin_scale=ks)
+    assert_close(plan.unpack(r["hpsi"]), want, TOL, "scaled hpsi")
+    e = r["energies"].cpu().numpy()     # energies of the unscaled operators
+    assert_scalar(e[0], full["e_loc"], TOL, "E_loc")
+    assert_scalar(e[1], full["e_kin"], TOL, "E_kin")
+
+
+def test_exact_engine_in_place_and_gradient_with_occupations():
+    cs = inputs.random_case(163, 4, (8, 16, 8), potential="gauss16")
+    occ = np.array([2.0, 1.5, 0.25, 1.0])
+    plan = ops.Plan(cs["dims"], prec="f32c", occ=occ)
+    ref = W.local_hpsi(cs["C"], cs["V"], occ)
+    c = plan.pack(cs["C"])
+    V = plan.pack_potential(cs["V"])
+    r = plan.local_hpsi(c, V, out=c)
+    assert_close(plan.unpack(c), list(ref["hpsi"]), TOL, "in-place hpsi")
+    g = plan.energy_gradient(plan.pack(cs["C"]), V)
+    want = [2.0 * f * h for f, h in zip(occ, ref["hpsi"])]
+    assert_close(plan.unpack(g), want, TOL, "gradient 2 f H c")
+
+
+def test_exact_engine_plane_exponents():
+    """Orbitals of very different magnitudes and an all-zero one in one batch:
+    every plane is split with its own exponent."""
+    cs = inputs.random_case(164, 4, (8, 8, 16), potential="gauss16")
+    C = cs["C"].copy()
+    C[0] *= 1e-20
+    C[1] *= 1e15
+    C[2] = 0.0
+    plan = ops.Plan(cs["dims"], prec="f32c")
+    ref = W.local_hpsi(C, cs["V"], cs["occ"])
+    r = plan.local_hpsi(plan.pack(C), plan.pack_potential(cs["V"]), per_orbital=True)
+    got = plan.unpack(r["hpsi"])
+    for b in (0, 1, 3):
+        assert_close(got[b], ref["hpsi"][b], TOL, f"orbital {b}")
+    assert not np.any(got[2])
+    eo = r["e_orb"].cpu().numpy()
+    for b in (0, 1, 3):
+        assert_scalar(eo[b], ref["e_loc_orb"][b], TOL, f"e_pot {b}")
+        assert_scalar(eo[plan.norb + b], ref["e_kin_orb"][b], TOL, f"e_kin {b}")
+
+
+def test_exact_engine_is_deterministic_and_graph_replays():
+    cs = inputs.random_case(165, 3, (16, 8, 8), potential="gauss16")
+    plan = ops.Plan(cs["dims"], prec="f32c")
+    gplan = ops.Plan(cs["dims"], prec="f32c", graph=True)
+    c, V = plan.pack(cs["C"]), plan.pack_potential(cs["V"])
+    r1 = plan.local_hpsi(c, V)
+    r2 = plan.local_hpsi(c, V)
+    assert torch.equal(r1["hpsi"], r2["hpsi"]) and torch.equal(r1["rho"], r2["rho"])
+    for _ in range(3):
+        rg = gplan.local_hpsi(c, V)
+        torch.cuda.synchronize()
+        assert torch.equal(rg["hpsi"], r1["hpsi"]) and torch.equal(rg["energies"], r1["energies"])
