@@ -34,8 +34,8 @@ namespace wvl {
 typedef int v4i __attribute__((ext_vector_type(4)));
 
 constexpr int kOzDig = 6;            // base-256 digits per value
-constexpr int kOzMaxTiles = 40;      // 16 x 16 tiles of a plane (up to 96 x 96 or 64 x 160)
-constexpr int kOzMaxQuads = 3072;    // 4-value quads of a plane (m1 m2 <= 12288)
+constexpr int kOzMaxTiles = 36;      // 16 x 16 tiles of a plane (up to 96 x 96 or 48 x 192)
+constexpr int kOzMaxQuads = 2304;    // 4-value quads of a plane (m1 m2 <= 9216)
 constexpr uint64_t kOzC = 0x808080808080ull;   // 128 in every digit: balanced digits by XOR
 // per workgroup of NW waves: tiles per wave and pass, quads per thread
 constexpr int oz_mt(int nw) { return (kOzMaxTiles + nw - 1) / nw; }
@@ -149,12 +149,14 @@ __device__ __forceinline__ int oz_exp_of(float maxhi) {
 }
 
 // X = round((hi + lo) 2^s) as an int64 (|X| < 0.99 2^47 for s = 47 - e)
+// (the integer part of hi 2^(s - 24) is exact; its fraction times 2^24 plus
+// lo 2^s is below 2^24 + 2^22 and rounds once in the fused multiply-add:
+// |error| <= 1.5)
 __device__ __forceinline__ int64_t oz_fix(float hi, float lo, int s) {
-  const float v = rintf(ldexpf(hi, s));
-  const float w = rintf(ldexpf(lo, s));
-  const float vh = truncf(v * 0x1p-24f);
-  const float vl = __builtin_fmaf(vh, -0x1p24f, v);     // exact: |vl| < 2^24
-  return (int64_t)(int32_t)vh * 16777216LL + (int64_t)((int32_t)vl + (int32_t)w);
+  const float v = ldexpf(hi, s - 24);                 // |v| < 2^23
+  const float vh = truncf(v);
+  const float w = rintf(__builtin_fmaf(v - vh, 0x1p24f, ldexpf(lo, s)));
+  return (int64_t)(int32_t)vh * 16777216LL + (int64_t)(int32_t)w;
 }
 
 // 2^E T as a float pair (hi, lo), |lo| <= ulp(hi) / 2
@@ -172,6 +174,43 @@ __device__ __forceinline__ f2 oz_tof(int64_t T, int E) {
 // 2^E T as a double (density and energy sums)
 __device__ __forceinline__ double oz_tod(int64_t T, int E) {
   return ldexp(__builtin_fma((double)(int32_t)(T >> 32), 4294967296.0, (double)(uint32_t)T), E);
+}
+
+// Compact float pairs of the intermediate arrays (6 bytes a value): the hi
+// float plane, then the lo part as an int16 plane in units of 2^-16 ulp(hi)
+// (|lo| <= ulp(hi) / 2, so |q| <= 2^15; relative error <= 2^-40).
+__device__ __forceinline__ int oz_ulp_exp(float hi) {    // log2 ulp(hi) - 16
+  const int eb = (__float_as_int(hi) >> 23) & 255;
+  return (eb > 1 ? eb : 1) - 166;
+}
+__device__ __forceinline__ int16_t oz_lo16(float hi, float lo) {
+  const float q = rintf(ldexpf(lo, -oz_ulp_exp(hi)));
+  return (int16_t)(int)fminf(fmaxf(q, -32767.0f), 32767.0f);
+}
+__device__ __forceinline__ float oz_lo_of(float hi, int16_t q) {
+  return ldexpf((float)q, oz_ulp_exp(hi));
+}
+__device__ __forceinline__ const int16_t* oz_lo_plane(const float* base, int64_t plane) {
+  return reinterpret_cast<const int16_t*>(base + plane);
+}
+__device__ __forceinline__ int16_t* oz_lo_plane(float* base, int64_t plane) {
+  return reinterpret_cast<int16_t*>(base + plane);
+}
+// four consecutive values at `at` (a multiple of 4)
+__device__ __forceinline__ void oz_store4_cp(float* base, int64_t plane, int64_t at, const f2 (&r)[4]) {
+  *reinterpret_cast<float4*>(base + at) = make_float4(r[0].hi, r[1].hi, r[2].hi, r[3].hi);
+  uint2 w;
+  w.x = (uint32_t)(uint16_t)oz_lo16(r[0].hi, r[0].lo) | ((uint32_t)(uint16_t)oz_lo16(r[1].hi, r[1].lo) << 16);
+  w.y = (uint32_t)(uint16_t)oz_lo16(r[2].hi, r[2].lo) | ((uint32_t)(uint16_t)oz_lo16(r[3].hi, r[3].lo) << 16);
+  *reinterpret_cast<uint2*>(oz_lo_plane(base, plane) + at) = w;
+}
+__device__ __forceinline__ void oz_load4_cp(const float* base, int64_t plane, int64_t at, f2 (&r)[4]) {
+  const float4 h = *reinterpret_cast<const float4*>(base + at);
+  const uint2 w = *reinterpret_cast<const uint2*>(oz_lo_plane(base, plane) + at);
+  r[0] = f2{h.x, oz_lo_of(h.x, (int16_t)(w.x & 0xffff))};
+  r[1] = f2{h.y, oz_lo_of(h.y, (int16_t)(w.x >> 16))};
+  r[2] = f2{h.z, oz_lo_of(h.z, (int16_t)(w.y & 0xffff))};
+  r[3] = f2{h.w, oz_lo_of(h.w, (int16_t)(w.y >> 16))};
 }
 
 // balanced digits of X (|X| < 0.99 2^47): bytes of Z, digit 5 in byte 0
@@ -226,6 +265,10 @@ __host__ __device__ inline int oz_pitch(int mc) {
   return c << 4;
 }
 
+// row pitch (doubles) of the density plane kept in LDS: 4 (mod 32), so that
+// 16 lanes reading 4 doubles each from 16 consecutive rows spread over the banks
+__host__ __device__ inline int oz_rho_pitch(int m1) { return m1 + ((36 - (m1 & 31)) & 31); }
+
 // block-wide max of v (all threads get it), NW waves
 template <int NW>
 __device__ __forceinline__ float oz_block_max(float v) {
@@ -261,32 +304,54 @@ __device__ __forceinline__ double oz_block_sum(double v) {
 // ROWS: ks == 1 (4 consecutive k per 16-byte load); otherwise ls == 1 and
 // each thread loads 4 values of one column.  e < -1000: take the plane's
 // exponent from its values (block max); returns the exponent used.
-template <bool ROWS, int NW>
+// CP: the source is a compact pair array (hi floats, int16 lo plane).
+template <bool ROWS, int NW, bool CP = false>
 __device__ __forceinline__ int oz_load(const float* src, int64_t plane, int64_t gp, int64_t stride,
                                        const OzGeo& g_, uint8_t* dst, int e) {
   const OzGeo g = oz_opaque(g_);
   constexpr int Q = oz_q(NW);
   const int nq = (g.mc >> 2) * g.mo;
+  // quad i of this thread: qd = tid + i 64 NW, at (line L, index k); ROWS
+  // steps along lines of mc / 4 quads, otherwise along columns of mo quads.
+  // (L, k) are stepped incrementally (one division per call).
+  const int per = ROWS ? (g.mc >> 2) : g.mo;        // quads per row of the quad grid
+  const int dq = (64 * NW) / per, dr = 64 * NW - dq * per;
+  int qa = (int)threadIdx.x / per, qb = (int)threadIdx.x - qa * per;
+  int La[Q], ka[Q];
+  #pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    La[i] = ROWS ? qa : qb;
+    ka[i] = ROWS ? qb << 2 : qa << 2;
+    qa += dq;
+    qb += dr;
+    if (qb >= per) { qb -= per; ++qa; }
+  }
   float h[Q][4], l[Q][4];
   float m = 0.0f;
   #pragma unroll
   for (int i = 0; i < Q; ++i) {
     const int qd = threadIdx.x + i * 64 * NW;
     if (qd < nq) {
+      const int L = La[i], k = ka[i];
       if (ROWS) {
-        const int L = qd / (g.mc >> 2), k = (qd - L * (g.mc >> 2)) << 2;
         const int64_t a = gp + (int64_t)L * stride + k;
-        const float4 hv = *reinterpret_cast<const float4*>(src + a);
-        const float4 lv = *reinterpret_cast<const float4*>(src + plane + a);
-        h[i][0] = hv.x; h[i][1] = hv.y; h[i][2] = hv.z; h[i][3] = hv.w;
-        l[i][0] = lv.x; l[i][1] = lv.y; l[i][2] = lv.z; l[i][3] = lv.w;
+        if (CP) {
+          f2 r[4];
+          oz_load4_cp(src, plane, a, r);
+          #pragma unroll
+          for (int v = 0; v < 4; ++v) { h[i][v] = r[v].hi; l[i][v] = r[v].lo; }
+        } else {
+          const float4 hv = *reinterpret_cast<const float4*>(src + a);
+          const float4 lv = *reinterpret_cast<const float4*>(src + plane + a);
+          h[i][0] = hv.x; h[i][1] = hv.y; h[i][2] = hv.z; h[i][3] = hv.w;
+          l[i][0] = lv.x; l[i][1] = lv.y; l[i][2] = lv.z; l[i][3] = lv.w;
+        }
       } else {
-        const int L = qd % g.mo, k = (qd / g.mo) << 2;
         #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int64_t a = gp + (int64_t)(k + v) * stride + L;
           h[i][v] = src[a];
-          l[i][v] = src[plane + a];
+          l[i][v] = CP ? oz_lo_of(h[i][v], oz_lo_plane(src, plane)[a]) : src[plane + a];
         }
       }
       #pragma unroll
@@ -299,15 +364,12 @@ __device__ __forceinline__ int oz_load(const float* src, int64_t plane, int64_t 
   for (int i = 0; i < Q; ++i) {
     const int qd = threadIdx.x + i * 64 * NW;
     if (qd < nq) {
-      int L, k;
-      if (ROWS) { L = qd / (g.mc >> 2); k = (qd - L * (g.mc >> 2)) << 2; }
-      else { L = qd % g.mo; k = (qd / g.mo) << 2; }
       OzZ z[4];
       #pragma unroll
       for (int v = 0; v < 4; ++v) z[v] = oz_digits(oz_fix(h[i][v], l[i][v], s));
       uint32_t d[kOzDig];
       oz_pack(z, d);
-      uint8_t* p = dst + L * g.pitch + k;
+      uint8_t* p = dst + La[i] * g.pitch + ka[i];
       #pragma unroll
       for (int q = 0; q < kOzDig; ++q) *reinterpret_cast<uint32_t*>(p + q * g.dstride) = d[q];
     }
@@ -315,29 +377,32 @@ __device__ __forceinline__ int oz_load(const float* src, int64_t plane, int64_t 
   return e;
 }
 
-// tile of this wave: default order (output block fastest) or YX, the
-// (y block, x block) order shared by an x pass and a y pass of one plane so
-// that both give a lane the same plane elements
+// The tiles of this wave (tile = wave + t NW) in one pass, enumerated with
+// scalar arithmetic (the wave index is uniform) and without a division per
+// tile: tile = a nb + b.  Order 0 (an x pass in (y block, x block) order, or
+// any pass): output block k0 = 16 b along the contracted axis (nb = mc / 16),
+// line block o0 = 16 a.  Order 2 (a y pass in (y block, x block) order,
+// lines x): k0 = 16 a, o0 = 16 b (nb = mo / 16), so that an x pass and a y
+// pass of one plane give a lane the same plane elements.
 template <int NW>
-__device__ __forceinline__ void oz_tile(int t, const OzGeo& g, int yx, int& k0, int& o0) {
-  const int tile = (threadIdx.x >> 6) + t * NW;
-  if (yx == 0) {
-    const int nk = g.mc >> 4;
-    const int ob = tile / nk;
-    k0 = (tile - ob * nk) << 4;
-    o0 = ob << 4;
-  } else if (yx == 1) {          // x pass (lines y, contracted x): tile = yb * nbx + xb
-    const int nbx = g.mc >> 4;
-    const int yb = tile / nbx;
-    k0 = (tile - yb * nbx) << 4;
-    o0 = yb << 4;
-  } else {                       // y pass (lines x, contracted y)
-    const int nbx = g.mo >> 4;
-    const int yb = tile / nbx;
-    k0 = yb << 4;
-    o0 = (tile - yb * nbx) << 4;
+struct OzTiles {
+  int a, b, nb, da, db;
+  __device__ __forceinline__ OzTiles(const OzGeo& g, int order) {
+    const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+    nb = order == 2 ? g.mo >> 4 : g.mc >> 4;
+    a = wave / nb;
+    b = wave - a * nb;
+    da = NW / nb;
+    db = NW - da * nb;
   }
-}
+  __device__ __forceinline__ int k0(int order) const { return (order == 2 ? a : b) << 4; }
+  __device__ __forceinline__ int o0(int order) const { return (order == 2 ? b : a) << 4; }
+  __device__ __forceinline__ void next() {
+    a += da;
+    b += db;
+    if (b >= nb) { b -= nb; ++a; }
+  }
+};
 
 // One pass of operator OP over the digit planes in `src`.  DA: data as the A
 // operand (rows = lines), else as the B operand (columns = lines).  For every
@@ -345,26 +410,40 @@ __device__ __forceinline__ void oz_tile(int t, const OzGeo& g, int yx, int& k0, 
 // the exact sums T[v] of the lane's four elements: (line o0 + 4 g + v, output
 // k0 + n) with DA, (output k0 + 4 g + v, line o0 + n) without, lane = n + 16 g;
 // value 2^(e + EF - 54) T[v] for input exponent e.
-template <int OP, bool DA, int NW, typename Epi>
+// RF: every step's filter digits held in registers for the whole pass (else
+// a two-step filter reloads them per tile and step, 24 registers fewer)
+template <int OP, bool DA, int NW, bool RF = true, typename Epi>
 __device__ __forceinline__ void oz_pass(const uint8_t* src, const OzGeo& g_, int yx, Epi&& epi) {
   using Fl = OzFilt<OP>;
   const OzGeo g = oz_opaque(g_);
   const int lane = threadIdx.x & 63, n = lane & 15, gq = lane >> 4;
   const int nt = (g.mc >> 4) * (g.mo >> 4);
+  const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+  const int order = yx == 2 ? 2 : 0;
+  OzTiles<NW> it(g, order);
+  // chunk offset of this lane's window in step st relative to k0, reduced
+  // into [0, mc) once per pass: the chunk starts at (k0 + off[st]) mod mc
+  int off[Fl::NSTEP];
+  #pragma unroll
+  for (int st = 0; st < Fl::NSTEP; ++st) {
+    int o = (-Fl::WOFF + 64 * st + 16 * gq) % g.mc;
+    off[st] = o < 0 ? o + g.mc : o;
+  }
+  const uint8_t* lane_src = src + n * g.pitch;
   const uint32_t* ft = oz_frag_tab<OP>();
   asm volatile("" : "+s"(ft));     // keep the table loads inside the pass
-  v4i f0[kOzDig];
-  if (Fl::NSTEP == 1) {
+  constexpr int NR = (RF || Fl::NSTEP == 1) ? Fl::NSTEP : 0;   // steps held in registers
+  v4i f0[NR > 0 ? NR : 1][kOzDig];
+  #pragma unroll
+  for (int st = 0; st < NR; ++st)
     #pragma unroll
     for (int q = 0; q < kOzDig; ++q)
-      f0[q] = *reinterpret_cast<const v4i*>(ft + (q * 64 + lane) * 4);
-  }
+      f0[st][q] = *reinterpret_cast<const v4i*>(ft + ((st * kOzDig + q) * 64 + lane) * 4);
   #pragma unroll
-  for (int t = 0; t < oz_mt(NW); ++t) {
-    if ((threadIdx.x >> 6) + t * NW >= nt) break;
-    int k0, o0;
-    oz_tile<NW>(t, g, yx, k0, o0);
-    const uint8_t* lp = src + (o0 + n) * g.pitch;
+  for (int t = 0; t < oz_mt(NW); ++t, it.next()) {
+    if (wave + t * NW >= nt) break;
+    const int k0 = it.k0(order), o0 = it.o0(order);
+    const uint8_t* lp = lane_src + o0 * g.pitch;
     v4i acc[kOzDig];
     #pragma unroll
     for (int s = 0; s < kOzDig; ++s) acc[s] = v4i{0, 0, 0, 0};
@@ -373,11 +452,10 @@ __device__ __forceinline__ void oz_pass(const uint8_t* src, const OzGeo& g_, int
       v4i f[kOzDig];
       #pragma unroll
       for (int q = 0; q < kOzDig; ++q)
-        f[q] = Fl::NSTEP == 1 ? f0[q]
-                              : *reinterpret_cast<const v4i*>(ft + ((st * kOzDig + q) * 64 + lane) * 4);
-      int c0 = k0 - Fl::WOFF + 64 * st + 16 * gq;
-      c0 %= g.mc;
-      c0 = c0 < 0 ? c0 + g.mc : c0;
+        f[q] = st < NR ? f0[st < NR ? st : 0][q]
+                       : *reinterpret_cast<const v4i*>(ft + ((st * kOzDig + q) * 64 + lane) * 4);
+      int c0 = k0 + off[st];
+      c0 = c0 >= g.mc ? c0 - g.mc : c0;
       // data digit i against filter digits j <= 5 - i; the next digit's LDS
       // read is issued before this digit's products (two digits in flight)
       const uint8_t* dp = lp + c0;
@@ -427,12 +505,13 @@ __device__ __forceinline__ void oz_store_packed(const OzPacked<NW>& pk, const Oz
                                                 uint8_t* dst, const OzGeo& gn_) {
   const OzGeo g = oz_opaque(g_), gn = oz_opaque(gn_);
   const int lane = threadIdx.x & 63, n = lane & 15, gq = lane >> 4;
+  const int order = yx == 2 ? 2 : 0;
+  OzTiles<NW> it(g, order);
+  uint8_t* lane_dst = dst + n * gn.pitch + 4 * gq;
   #pragma unroll
-  for (int t = 0; t < oz_mt(NW); ++t) {
+  for (int t = 0; t < oz_mt(NW); ++t, it.next()) {
     if (t >= pk.n) break;
-    int k0, o0;
-    oz_tile<NW>(t, g, yx, k0, o0);
-    uint8_t* p = dst + (k0 + n) * gn.pitch + o0 + 4 * gq;
+    uint8_t* p = lane_dst + it.k0(order) * gn.pitch + it.o0(order);
     #pragma unroll
     for (int q = 0; q < kOzDig; ++q) *reinterpret_cast<uint32_t*>(p + q * gn.dstride) = pk.d[t][q];
   }

@@ -11,9 +11,10 @@
 //   final:  Hc = W_z^T t + kin_scale k (K_z c + kxy), e_kin   over xz-planes
 // with W = CW, W^T = CWT, K = CK the combined filters (Sec. 2.4, last
 // paragraph; Sec. 3.1 for the separable form) and k = -1/(2 h^2).  t, u and
-// kxy are float pairs in the workspace; every plane enters a kernel as float
-// pairs, is split into digits with its own exponent, and leaves as float
-// pairs (t, u, kxy, Hc) or float64 sums (rho, energies).
+// kxy are compact float pairs in the workspace (hi float, lo as an int16
+// fraction of ulp(hi): 6 bytes a value); every plane enters a kernel as
+// float pairs, is split into digits with its own exponent, and leaves as
+// float pairs (t, u, kxy, Hc) or float64 sums (rho, energies).
 #include <algorithm>
 
 #include "wvl_oz.h"
@@ -67,13 +68,8 @@ void k_oz_z(OzArgs a) {
   oz_pass<OP_CW, true, kOzZWaves>(oz_lds, gz, 0, [&](int, int k0, int o0, const int64_t (&T)[4]) {
     // elements (x = o0 + 4 g + v, z = k0 + n)
     const int64_t at = gp + (int64_t)(k0 + n) * zs + o0 + 4 * gq;
-    float4 h, l;
-    f2 r = oz_tof(T[0], E); h.x = r.hi; l.x = r.lo;
-    r = oz_tof(T[1], E); h.y = r.hi; l.y = r.lo;
-    r = oz_tof(T[2], E); h.z = r.hi; l.z = r.lo;
-    r = oz_tof(T[3], E); h.w = r.hi; l.w = r.lo;
-    *reinterpret_cast<float4*>(u + at) = h;
-    *reinterpret_cast<float4*>(u + a.plane + at) = l;
+    const f2 r[4] = {oz_tof(T[0], E), oz_tof(T[1], E), oz_tof(T[2], E), oz_tof(T[3], E)};
+    oz_store4_cp(u, a.plane, at, r);
   });
 }
 
@@ -93,7 +89,7 @@ __device__ __forceinline__ void oz_xy_plane(const OzArgs& a, int b, int z, int b
   const int lane = threadIdx.x & 63, n = lane & 15, gq = lane >> 4;
 
   // ---- psi = W_y W_x u
-  int e = oz_load<true, NW>(a.u, a.plane, gp, m1, gx, lds, -2000);
+  int e = oz_load<true, NW, true>(a.u, a.plane, gp, m1, gx, lds, -2000);
   __syncthreads();
   oz_pass_to_digits<OP_CW, NW>(lds, gx, gy);
   e += OzK<OP_CW>::GF;
@@ -112,12 +108,13 @@ __device__ __forceinline__ void oz_xy_plane(const OzArgs& a, int b, int z, int b
     oz_pass<OP_CW, true, NW>(lds, gy, 0, [&](int t, int k0, int o0, const int64_t (&T)[4]) {
       // elements (x = o0 + 4 g + v, y = k0 + n): four consecutive x of row y
       const int pe = (k0 + n) * m1 + o0 + 4 * gq;
+      const int pr = (k0 + n) * oz_rho_pitch(m1) + o0 + 4 * gq;   // in the LDS density plane
       const float4 h4 = *reinterpret_cast<const float4*>(vh + pe);
       const float4 l4 = *reinterpret_cast<const float4*>(vl + pe);
       const float hv[4] = {h4.x, h4.y, h4.z, h4.w}, lv[4] = {l4.x, l4.y, l4.z, l4.w};
       double r4[4] = {0.0, 0.0, 0.0, 0.0};
       if (bi != 0) {
-        const double4 q = *reinterpret_cast<const double4*>(rho_l + pe);
+        const double4 q = *reinterpret_cast<const double4*>(rho_l + pr);
         r4[0] = q.x; r4[1] = q.y; r4[2] = q.z; r4[3] = q.w;
       }
       OzZ zz[4];
@@ -131,7 +128,7 @@ __device__ __forceinline__ void oz_xy_plane(const OzArgs& a, int b, int z, int b
         if (a.ps_scaled) yv = oz_mul(yv, ps);
         zz[v] = oz_digits(oz_fix(yv.hi, yv.lo, 47 - ey));
       }
-      *reinterpret_cast<double4*>(rho_l + pe) = make_double4(r4[0], r4[1], r4[2], r4[3]);
+      *reinterpret_cast<double4*>(rho_l + pr) = make_double4(r4[0], r4[1], r4[2], r4[3]);
       oz_pack(zz, pk.d[t]);
       pk.n = t + 1;
     });
@@ -148,13 +145,8 @@ __device__ __forceinline__ void oz_xy_plane(const OzArgs& a, int b, int z, int b
     float* tp = a.t;
     oz_pass<OP_CWT, true, NW>(lds, gy, 0, [&](int, int k0, int o0, const int64_t (&T)[4]) {
       const int64_t at = gp + (int64_t)(k0 + n) * m1 + o0 + 4 * gq;
-      float4 h, l;
-      f2 r = oz_tof(T[0], Et); h.x = r.hi; l.x = r.lo;
-      r = oz_tof(T[1], Et); h.y = r.hi; l.y = r.lo;
-      r = oz_tof(T[2], Et); h.z = r.hi; l.z = r.lo;
-      r = oz_tof(T[3], Et); h.w = r.hi; l.w = r.lo;
-      *reinterpret_cast<float4*>(tp + at) = h;
-      *reinterpret_cast<float4*>(tp + a.plane + at) = l;
+      const f2 r[4] = {oz_tof(T[0], Et), oz_tof(T[1], Et), oz_tof(T[2], Et), oz_tof(T[3], Et)};
+      oz_store4_cp(tp, a.plane, at, r);
     });
     __syncthreads();
   }
@@ -165,7 +157,7 @@ __device__ __forceinline__ void oz_xy_plane(const OzArgs& a, int b, int z, int b
   const int ec = oz_load<true, NW>(a.c, a.plane, gp, m1, gx, lds, -2000);
   __syncthreads();
   int64_t Tx[oz_mt(NW)][4];
-  oz_pass<OP_CK, true, NW>(lds, gx, 1, [&](int t, int, int, const int64_t (&T)[4]) {
+  oz_pass<OP_CK, true, NW, false>(lds, gx, 1, [&](int t, int, int, const int64_t (&T)[4]) {
     #pragma unroll
     for (int v = 0; v < 4; ++v) Tx[t][v] = T[v];
   });
@@ -175,14 +167,14 @@ __device__ __forceinline__ void oz_xy_plane(const OzArgs& a, int b, int z, int b
   {
     const int Ek = ec + OzK<OP_CK>::EF - 54;
     float* kp = a.kxy;
-    oz_pass<OP_CK, false, NW>(lds, gy, 2, [&](int t, int k0, int o0, const int64_t (&T)[4]) {
+    oz_pass<OP_CK, false, NW, false>(lds, gy, 2, [&](int t, int k0, int o0, const int64_t (&T)[4]) {
       // elements (y = k0 + 4 g + v, x = o0 + n)
       #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const f2 r = oz_tof(T[v] + Tx[t][v], Ek);
         const int64_t at = gp + (int64_t)(k0 + 4 * gq + v) * m1 + o0 + n;
         kp[at] = r.hi;
-        kp[a.plane + at] = r.lo;
+        oz_lo_plane(kp, a.plane)[at] = oz_lo16(r.hi, r.lo);
       }
     });
   }
@@ -205,10 +197,13 @@ void k_oz_xy(OzArgs a) {
   }
   // the group's density partial of this plane, once
   __syncthreads();
-  const int npl = a.m1 * a.m2;
+  const int npl = a.m1 * a.m2, rpitch = oz_rho_pitch(a.m1), half = a.m1 >> 1;
   double* rp = a.rho_part + (int64_t)g * a.M + (int64_t)z * npl;
-  for (int e = 2 * threadIdx.x; e < npl; e += 2 * 64 * kOzXyWaves)
-    *reinterpret_cast<double2*>(rp + e) = *reinterpret_cast<const double2*>(rho_l + e);
+  for (int e = threadIdx.x; e < (npl >> 1); e += 64 * kOzXyWaves) {
+    const int y = e / half, x = (e - y * half) << 1;
+    *reinterpret_cast<double2*>(rp + y * a.m1 + x) =
+        *reinterpret_cast<const double2*>(rho_l + y * rpitch + x);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -226,7 +221,7 @@ void k_oz_zfinal(OzArgs a) {
   const OzGeo gz{m3, m1, oz_pitch(m3), a.dz};
   const int lane = threadIdx.x & 63, n = lane & 15, gq = lane >> 4;
   constexpr int NW = kOzZWaves;
-  const int et = oz_load<false, NW>(a.t, a.plane, gp, zs, gz, oz_lds, -2000);
+  const int et = oz_load<false, NW, true>(a.t, a.plane, gp, zs, gz, oz_lds, -2000);
   __syncthreads();
   int64_t Tt[oz_mt(NW)][4];
   oz_pass<OP_CWT, true, NW>(oz_lds, gz, 0, [&](int t, int, int, const int64_t (&T)[4]) {
@@ -247,19 +242,18 @@ void k_oz_zfinal(OzArgs a) {
   const float* kxy = a.kxy;
   const float* c = a.c;
   float* out = a.out;
-  oz_pass<OP_CK, true, NW>(oz_lds, gz, 0, [&](int t, int k0, int o0, const int64_t (&T)[4]) {
+  oz_pass<OP_CK, true, NW, false>(oz_lds, gz, 0, [&](int t, int k0, int o0, const int64_t (&T)[4]) {
     // elements (x = o0 + 4 g + v, z = k0 + n)
     const int64_t at = gp + (int64_t)(k0 + n) * zs + o0 + 4 * gq;
-    const float4 kh4 = *reinterpret_cast<const float4*>(kxy + at);
-    const float4 kl4 = *reinterpret_cast<const float4*>(kxy + a.plane + at);
+    f2 kx[4];
+    oz_load4_cp(kxy, a.plane, at, kx);
     const float4 ch4 = *reinterpret_cast<const float4*>(c + at);
     const float4 cl4 = *reinterpret_cast<const float4*>(c + a.plane + at);
-    const float khv[4] = {kh4.x, kh4.y, kh4.z, kh4.w}, klv[4] = {kl4.x, kl4.y, kl4.z, kl4.w};
     const float chv[4] = {ch4.x, ch4.y, ch4.z, ch4.w}, clv[4] = {cl4.x, cl4.y, cl4.z, cl4.w};
     float oh[4], ol[4];
     #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const f2 kc = oz_mul(oz_add(oz_tof(T[v], Ek), f2{khv[v], klv[v]}), ks);
+      const f2 kc = oz_mul(oz_add(oz_tof(T[v], Ek), kx[v]), ks);
       ek = __builtin_fma((double)chv[v] + (double)clv[v], oz_pair_d(kc), ek);
       const f2 o = oz_add(oz_tof(Tt[t][v], Et), a.km_scaled ? oz_mul(kc, km) : kc);
       oh[v] = o.hi;
@@ -282,7 +276,7 @@ OzLds oz_lds(int m1, int m2, int m3) {
   const int axy = std::max(m2 * oz_pitch(m1), m1 * oz_pitch(m2));
   r.dxy = (axy + 15) & ~15;
   r.dz = (m1 * oz_pitch(m3) + 15) & ~15;
-  r.xy_bytes = (size_t)kOzDig * r.dxy + sizeof(double) * (size_t)m1 * m2;   // digits + rho plane
+  r.xy_bytes = (size_t)kOzDig * r.dxy + sizeof(double) * (size_t)oz_rho_pitch(m1) * m2;   // + rho
   r.z_bytes = (size_t)kOzDig * r.dz;
   return r;
 }
