@@ -60,6 +60,40 @@ __device__ __forceinline__ void load4(const void* X, int64_t plane, int64_t row,
   }
 }
 
+// N (2, 4 or 8) consecutive values at element i (i a multiple of N; batch
+// lengths are multiples of 8) as float64, with vector loads
+template <int P, int N>
+__device__ __forceinline__ void ld_run(const void* X, int64_t plane, int64_t i, double (&v)[N]) {
+  if (P == F64) {
+    const double2* p = reinterpret_cast<const double2*>((const double*)X + i);
+    #pragma unroll
+    for (int u = 0; u < N / 2; ++u) {
+      const double2 d = p[u];
+      v[2 * u] = d.x;
+      v[2 * u + 1] = d.y;
+    }
+  } else if (N == 2) {
+    const float2 a = *reinterpret_cast<const float2*>((const float*)X + i);
+    float2 b = make_float2(0.f, 0.f);
+    if (P == F32C) b = *reinterpret_cast<const float2*>((const float*)X + plane + i);
+    v[0] = (double)a.x + (double)b.x;
+    v[1] = (double)a.y + (double)b.y;
+  } else {
+    const float4* h = reinterpret_cast<const float4*>((const float*)X + i);
+    const float4* l = reinterpret_cast<const float4*>((const float*)X + plane + i);
+    #pragma unroll
+    for (int u = 0; u < N / 4; ++u) {
+      const float4 a = h[u];
+      float4 b = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (P == F32C) b = l[u];
+      v[4 * u] = (double)a.x + (double)b.x;
+      v[4 * u + 1] = (double)a.y + (double)b.y;
+      v[4 * u + 2] = (double)a.z + (double)b.z;
+      v[4 * u + 3] = (double)a.w + (double)b.w;
+    }
+  }
+}
+
 // grid: one wave per (slice, lower-triangle block); the blocks of one slice
 // share blockIdx.x mod 8, i.e. run on one XCD.
 template <int P>
@@ -167,6 +201,10 @@ __global__ __launch_bounds__(512) void k_syrk32(const void* __restrict__ X, int6
   const int srow = tid >> 1, shalf = (tid & 1) * 8;
   double stage[8];
   auto fetch = [&](int64_t k) {
+    if (srow < norb && k + shalf + 8 <= k1) {
+      ld_run<P, 8>(X, plane, (int64_t)srow * len + k + shalf, stage);
+      return;
+    }
     #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int64_t kk = k + shalf + u;
@@ -524,6 +562,10 @@ __global__ __launch_bounds__(512) void k_trmm2(const double* __restrict__ Li, co
   double xs[2];
   auto fetch = [&](int kc) {
     const int row = 16 * kc + sr;
+    if (row < n && c0 + sc + 2 <= len) {
+      ld_run<P, 2>(X, plane, (int64_t)row * len + c0 + sc, xs);
+      return;
+    }
     #pragma unroll
     for (int u = 0; u < 2; ++u) {
       const int64_t col = c0 + sc + u;
