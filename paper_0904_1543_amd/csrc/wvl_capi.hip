@@ -897,9 +897,7 @@ int hpsi_oz(wvl_plan* p, hipStream_t st, const void* c, const double* V, double 
   a.ps_hi = (float)pot_scale;
   a.ps_lo = (float)(pot_scale - (double)a.ps_hi);
   a.ps_scaled = pot_scale != 1.0;
-  a.km_hi = (float)kin_scale;
-  a.km_lo = (float)(kin_scale - (double)a.km_hi);
-  a.km_scaled = kin_scale != 1.0;
+  a.kin_mul = kin_scale;
   a.rho_part = rhop;
   a.ngroups = p->xy_ngroups;
   a.G = p->xy_G;

@@ -197,8 +197,9 @@ struct OzArgs {
   const int* vexp;       // per z-plane exponent of max |V|
   int64_t M;
   int32_t pexp;          // |pot_scale| <= 2^pexp
-  float ps_hi, ps_lo, km_hi, km_lo;   // pot_scale and kin_scale as float pairs
-  int32_t ps_scaled, km_scaled;       // != 1
+  float ps_hi, ps_lo;    // pot_scale as a float pair
+  int32_t ps_scaled;     // pot_scale != 1
+  double kin_mul;        // kin_scale
   double* rho_part;      // [ngroups][M] group partials
   int32_t ngroups, G;
   double* epot;          // per (orbital, z-plane) at pq[b] + z

@@ -159,7 +159,10 @@ __device__ __forceinline__ int64_t oz_fix(float hi, float lo, int s) {
   return (int64_t)(int32_t)vh * 16777216LL + (int64_t)(int32_t)w;
 }
 
-// 2^E T as a float pair (hi, lo), |lo| <= ulp(hi) / 2
+// 2^E T as a float pair (hi, lo), |lo| <= ulp(hi) / 2.  a 2^32 is the high
+// word rounded to a float and fr the rest (below 2^32 when the high word is
+// exact, below the high part's ulp otherwise), so |a 2^32| >= |fr| or a = 0:
+// the fast two-sum is exact.
 __device__ __forceinline__ f2 oz_tof(int64_t T, int E) {
   const int32_t th = (int32_t)(T >> 32);
   const uint32_t tl = (uint32_t)T;
@@ -167,7 +170,7 @@ __device__ __forceinline__ f2 oz_tof(int64_t T, int E) {
   const int32_t rh = th - (int32_t)a;
   const float fr = __builtin_fmaf((float)rh, 0x1p32f, (float)tl);
   f2 r;
-  two_sum(ldexpf(a, E + 32), ldexpf(fr, E), r.hi, r.lo);
+  fast_two_sum(ldexpf(a, E + 32), ldexpf(fr, E), r.hi, r.lo);
   return r;
 }
 
@@ -375,6 +378,60 @@ __device__ __forceinline__ int oz_load(const float* src, int64_t plane, int64_t 
     }
   }
   return e;
+}
+
+// Digits of a plane in layout g ([y][x]: lines y of mc = m1 bytes) rewritten
+// in layout gt ([x][y]), in place: each thread moves 4 x 4 blocks (4 rows of
+// one 4-byte word per digit plane, transposed with byte permutes); a wave
+// covers 8 x 8 blocks (rows and columns in steps of 4 lines: at most two
+// lanes per bank).  All blocks are read before the barrier, written after it.
+template <int NW>
+__device__ __forceinline__ void oz_transpose(uint8_t* lds, const OzGeo& g_, const OzGeo& gt_) {
+  const OzGeo g = oz_opaque(g_), gt = oz_opaque(gt_);
+  const int nbx = g.mc >> 2, nby = g.mo >> 2;             // 4 x 4 blocks along x and y
+  const int wtx = (nbx + 7) >> 3, wty = (nby + 7) >> 3;   // 8 x 8 block tiles
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+  constexpr int KB = (kOzMaxQuads / 4 + 64 * NW - 1) / (64 * NW);   // block tiles per wave
+  uint32_t d[KB][kOzDig][4];
+  int bx[KB], by[KB];
+  bool ok[KB];
+  #pragma unroll
+  for (int r = 0; r < KB; ++r) {
+    const int wt = wave + r * NW;
+    const int ty = wt / (wtx > 0 ? wtx : 1), tx = wt - ty * wtx;
+    bx[r] = tx * 8 + (lane & 7);
+    by[r] = ty * 8 + (lane >> 3);
+    ok[r] = wt < wtx * wty && bx[r] < nbx && by[r] < nby;
+    if (ok[r]) {
+      const uint8_t* src = lds + (4 * by[r]) * g.pitch + 4 * bx[r];
+      #pragma unroll
+      for (int q = 0; q < kOzDig; ++q)
+        #pragma unroll
+        for (int rr = 0; rr < 4; ++rr)
+          d[r][q][rr] = *reinterpret_cast<const uint32_t*>(src + q * g.dstride + rr * g.pitch);
+    }
+  }
+  __syncthreads();
+  #pragma unroll
+  for (int r = 0; r < KB; ++r) {
+    if (!ok[r]) continue;
+    uint8_t* dst = lds + (4 * bx[r]) * gt.pitch + 4 * by[r];
+    #pragma unroll
+    for (int q = 0; q < kOzDig; ++q) {
+      const uint32_t* D = d[r][q];
+      const uint32_t t01l = __builtin_amdgcn_perm(D[1], D[0], 0x05010400u);
+      const uint32_t t23l = __builtin_amdgcn_perm(D[3], D[2], 0x05010400u);
+      const uint32_t t01h = __builtin_amdgcn_perm(D[1], D[0], 0x07030602u);
+      const uint32_t t23h = __builtin_amdgcn_perm(D[3], D[2], 0x07030602u);
+      uint8_t* o = dst + q * gt.dstride;
+      *reinterpret_cast<uint32_t*>(o) = __builtin_amdgcn_perm(t23l, t01l, 0x05040100u);
+      *reinterpret_cast<uint32_t*>(o + gt.pitch) = __builtin_amdgcn_perm(t23l, t01l, 0x07060302u);
+      *reinterpret_cast<uint32_t*>(o + 2 * gt.pitch) = __builtin_amdgcn_perm(t23h, t01h, 0x05040100u);
+      *reinterpret_cast<uint32_t*>(o + 3 * gt.pitch) = __builtin_amdgcn_perm(t23h, t01h, 0x07060302u);
+    }
+  }
+  __syncthreads();
 }
 
 // The tiles of this wave (tile = wave + t NW) in one pass, enumerated with

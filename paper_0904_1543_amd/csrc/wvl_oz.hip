@@ -162,8 +162,7 @@ __device__ __forceinline__ void oz_xy_plane(const OzArgs& a, int b, int z, int b
     for (int v = 0; v < 4; ++v) Tx[t][v] = T[v];
   });
   __syncthreads();
-  oz_load<false, NW>(a.c, a.plane, gp, m1, gy, lds, ec);
-  __syncthreads();
+  oz_transpose<NW>(lds, gx, gy);      // c's digits in [x][y] for the y pass
   {
     const int Ek = ec + OzK<OP_CK>::EF - 54;
     float* kp = a.kxy;
@@ -233,11 +232,18 @@ void k_oz_zfinal(OzArgs a) {
   __syncthreads();
   const int Et = et + OzK<OP_CWT>::EF - 54;
   const int Ek = ec + OzK<OP_CK>::EF - 54;
-  // k = -1/(2 h^2) of this orbital (the same along every axis) as a float pair
-  const double kd = od.kscale[0];
+  // K c = K_z c + kxy (without k) as a float pair (kxy may exceed this
+  // xz-plane's own bound: K_y reaches rows up to 29 away); e_kin = k <c, K c>;
+  // Hc = W_z^T t + kd K c with kd = k kin_scale, a power of two in the usual
+  // case (exact scaling of the pair)
+  const double ks = od.kscale[0];
+  const double kd = ks * a.kin_mul;
+  int kx2 = 0;
+  const double kf = frexp(kd, &kx2);
+  const bool pow2 = kf == 0.5 || kf == -0.5;
+  const float ksign = kf < 0 ? -1.0f : 1.0f;
   const float kh = (float)kd;
-  const f2 ks{kh, (float)(kd - (double)kh)};
-  const f2 km{a.km_hi, a.km_lo};
+  const f2 kp{kh, (float)(kd - (double)kh)};
   double ek = 0.0;
   const float* kxy = a.kxy;
   const float* c = a.c;
@@ -250,20 +256,20 @@ void k_oz_zfinal(OzArgs a) {
     const float4 ch4 = *reinterpret_cast<const float4*>(c + at);
     const float4 cl4 = *reinterpret_cast<const float4*>(c + a.plane + at);
     const float chv[4] = {ch4.x, ch4.y, ch4.z, ch4.w}, clv[4] = {cl4.x, cl4.y, cl4.z, cl4.w};
-    float oh[4], ol[4];
+    f2 o[4];
     #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const f2 kc = oz_mul(oz_add(oz_tof(T[v], Ek), kx[v]), ks);
+      const f2 kc = oz_add(oz_tof(T[v], Ek), kx[v]);
       ek = __builtin_fma((double)chv[v] + (double)clv[v], oz_pair_d(kc), ek);
-      const f2 o = oz_add(oz_tof(Tt[t][v], Et), a.km_scaled ? oz_mul(kc, km) : kc);
-      oh[v] = o.hi;
-      ol[v] = o.lo;
+      const f2 sc = pow2 ? f2{ksign * ldexpf(kc.hi, kx2 - 1), ksign * ldexpf(kc.lo, kx2 - 1)}
+                         : oz_mul(kc, kp);
+      o[v] = oz_add(oz_tof(Tt[t][v], Et), sc);
     }
-    *reinterpret_cast<float4*>(out + at) = make_float4(oh[0], oh[1], oh[2], oh[3]);
-    *reinterpret_cast<float4*>(out + a.plane + at) = make_float4(ol[0], ol[1], ol[2], ol[3]);
+    *reinterpret_cast<float4*>(out + at) = make_float4(o[0].hi, o[1].hi, o[2].hi, o[3].hi);
+    *reinterpret_cast<float4*>(out + a.plane + at) = make_float4(o[0].lo, o[1].lo, o[2].lo, o[3].lo);
   });
-  const double sk = oz_block_sum<NW>(ek);
-  if (threadIdx.x == 0) a.ekin[(int64_t)b * a.m2 + y] = sk;
+  const double sk2 = oz_block_sum<NW>(ek);
+  if (threadIdx.x == 0) a.ekin[(int64_t)b * a.m2 + y] = ks * sk2;
 }
 
 }  // namespace
@@ -288,6 +294,8 @@ bool oz_supported(int m1, int m2, int m3) {
   const int txy = (m1 >> 4) * (m2 >> 4), txz = (m1 >> 4) * (m3 >> 4);
   if (txy > kOzMaxTiles || txz > kOzMaxTiles) return false;
   if (m1 * m2 / 4 > kOzMaxQuads || m1 * m3 / 4 > kOzMaxQuads) return false;
+  // the in-LDS transpose of c: one 8 x 8 block tile (32 x 32 values) per wave
+  if (((m1 + 31) / 32) * ((m2 + 31) / 32) > kOzXyWaves) return false;
   const OzLds l = oz_lds(m1, m2, m3);
   return l.xy_bytes <= 160 * 1024 && l.z_bytes <= 160 * 1024;
 }
