@@ -287,17 +287,25 @@ int wvl_plan_sync(wvl_plan *plan, void *stream);
  * with vector-FMA in-plane passes, chosen whenever every orbital's (x, y)
  * plane fits in LDS; 2: the same with the in-plane passes of WVL_F64 on the
  * float64 matrix cores, chosen for WVL_F64 when the plane fits their 16 x 16
- * tiling (up to 128 x 128).  Without WVL_AUTOTUNE the environment variable
- * WVL_NO_PLANE_KERNEL forces 0 and WVL_XY_VECTOR forces 1 over 2; the
- * variable WVL_PLANE_OCCUPANCY=2 compiles the plane kernel's choice for 2
- * instead of 4 waves per SIMD, and WVL_NO_ZFUSE runs the last z step as two
- * passes instead of one fused launch (same results bit for bit; the fused
- * launch is used for WVL_F64 and WVL_F32).)  With WVL_AUTOTUNE, times_ms[k]
- * (k < ntimes, at most 12 candidates) receives the mean time of candidate
- * k = 3 seq + shape, or -1 where it was not available:
+ * tiling (up to 128 x 128); 3: WVL_F32C with exact int8 digit products on
+ * the matrix cores (every pass of float pairs split into six base-256 digits
+ * per plane, the digit products summed exactly in int32, recombined in
+ * int64), chosen for WVL_F32C plans with WVL_SHARED_V, periodic boundaries,
+ * fine lengths that are multiples of 16, planes of at most 36 tiles of
+ * 16 x 16 and the same grid spacing along every axis of an orbital.  Without
+ * WVL_AUTOTUNE the environment variable WVL_NO_PLANE_KERNEL forces 0,
+ * WVL_F32C_VECTOR keeps WVL_F32C off variant 3 and WVL_XY_VECTOR forces 1
+ * over 2; the variable WVL_PLANE_OCCUPANCY=2 compiles
+ * the plane kernel's choice for 2 instead of 4 waves per SIMD,
+ * WVL_EXACT_OCCUPANCY_Z=2 the last z kernel of variant 3 for 2, and
+ * WVL_NO_ZFUSE runs the last z step as two passes instead of one fused
+ * launch (same results bit for bit; the fused launch is used for WVL_F64 and
+ * WVL_F32).)  With WVL_AUTOTUNE, times_ms[k] (k < ntimes, at most 15
+ * candidates) receives the mean time of candidate k = 3 seq + shape, or -1
+ * where it was not available:
  *   seq 0 one pass per axis; 1 plane kernel at 4 waves per SIMD (default
  *   engine); 2 the same at 2 waves per SIMD; 3 plane kernel with the vector
- *   engine (WVL_F64 only);
+ *   engine (WVL_F64 only); 4 the exact digit products (variant 3);
  *   shape 0 default tiles; 1 axis-1 tiles of half as many rows (seq 0 only);
  *   2 persistent launches of 4 instead of 8 workgroups per CU (WVL_PERSISTENT
  *   plans only).

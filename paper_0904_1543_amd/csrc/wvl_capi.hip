@@ -461,7 +461,8 @@ int wvl_plan_create(wvl_ctx* ctx, const wvl_orbital* orbs, int32_t norb, int32_t
   }
   // exact-product engine of the compensated form
   {
-    bool ok = prec == WVL_F32C && p->shared && !p->bc_any && !getenv("WVL_F32C_VECTOR");
+    bool ok = prec == WVL_F32C && p->shared && !p->bc_any && !getenv("WVL_F32C_VECTOR") &&
+              !getenv("WVL_NO_PLANE_KERNEL");
     if (ok) ok = oz_supported(p->orbs[0].m[0], p->orbs[0].m[1], p->orbs[0].m[2]);
     for (int b = 0; ok && b < norb; ++b) {
       const double* k = p->orbs[b].kscale;

@@ -268,3 +268,31 @@ def test_boundary_condition_plans(dry):
         assert lib.raw("wvl_precondition")(p, a, eps, 3, 1, b, None, ws, None) == \
             lib.WVL_EUNSUPPORTED                                   # separate form: periodic only
         lib.wvl_plan_destroy(p)
+
+
+def test_exact_product_engine_selection(dry, monkeypatch):
+    """Compensated plans take the exact digit-product engine (variant 3) when
+    it applies: shared potential, fine lengths multiples of 16, planes of at
+    most 36 tiles, isotropic spacing; otherwise the vector engine."""
+    q = lib.raw("wvl_plan_query")
+    v = ctypes.c_int64()
+
+    def variant(dims, flags=1, **kw):
+        rc, p = _plan(dry, dims, prec=2, flags=flags, **kw)
+        assert rc == lib.WVL_OK
+        assert q(p, lib.WVL_Q_VARIANT, ctypes.byref(v)) == lib.WVL_OK
+        lib.wvl_plan_destroy(p)
+        return v.value
+
+    assert variant([(48, 48, 48)] * 4) == 3                  # fine 96^3: 36 tiles a plane
+    assert variant([(8, 24, 16)] * 3) == 3                   # fine (32, 48, 16)
+    assert variant([(20, 18, 17)] * 2) == 1                  # lengths not multiples of 16
+    assert variant([(56, 48, 48)] * 2) == 1                  # 112 x 96 planes: 42 tiles
+    assert variant([(48, 48, 48)] * 2, flags=0) == 1         # one potential per orbital
+    assert variant([(16, 16, 16)] * 2, hgrid=(1.0, 0.9, 1.0)) == 1
+    assert variant([(16, 16, 16)] * 2, hgrid=(0.8, 0.8, 0.8)) == 3
+    monkeypatch.setenv("WVL_F32C_VECTOR", "1")
+    assert variant([(48, 48, 48)] * 4) == 1
+    monkeypatch.delenv("WVL_F32C_VECTOR")
+    monkeypatch.setenv("WVL_NO_PLANE_KERNEL", "1")
+    assert variant([(48, 48, 48)] * 4) == 0
