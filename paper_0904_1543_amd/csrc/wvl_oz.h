@@ -222,6 +222,17 @@ __device__ __forceinline__ OzZ oz_digits(int64_t X) {
   const uint64_t z = ((uint64_t)X + kOzC) ^ kOzC;
   return OzZ{(uint32_t)z, (uint32_t)(z >> 32)};
 }
+// X of value v (byte v of each digit plane's word dw[q], digit 0 most
+// significant): the inverse of oz_digits
+__device__ __forceinline__ int64_t oz_undigits(const uint32_t (&dw)[kOzDig], int v) {
+  const uint32_t sel = 0x0c0c0c00u | (uint32_t)v;       // byte v, then zeros
+  const uint32_t b5 = __builtin_amdgcn_perm(0u, dw[5], sel), b4 = __builtin_amdgcn_perm(0u, dw[4], sel);
+  const uint32_t b3 = __builtin_amdgcn_perm(0u, dw[3], sel), b2 = __builtin_amdgcn_perm(0u, dw[2], sel);
+  const uint32_t b1 = __builtin_amdgcn_perm(0u, dw[1], sel), b0 = __builtin_amdgcn_perm(0u, dw[0], sel);
+  const uint64_t z = ((uint64_t)(b1 | (b0 << 8)) << 32) | (b5 | (b4 << 8) | (b3 << 16) | (b2 << 24));
+  return (int64_t)((z ^ kOzC) - kOzC);
+}
+
 // digits of round(T 2^-R) (the next pass's fixed point), same form
 template <int R>
 __device__ __forceinline__ OzZ oz_digits_shift(int64_t T) {

@@ -222,8 +222,11 @@ void k_oz_zfinal(OzArgs a) {
   constexpr int NW = kOzZWaves;
   const int et = oz_load<false, NW, true>(a.t, a.plane, gp, zs, gz, oz_lds, -2000);
   __syncthreads();
+  // both passes with the data as the B operand: a lane holds four
+  // consecutive z of one line x, so that c's digits of its elements are one
+  // word per digit plane in LDS (the kinetic energy needs c there)
   int64_t Tt[oz_mt(NW)][4];
-  oz_pass<OP_CWT, true, NW>(oz_lds, gz, 0, [&](int t, int, int, const int64_t (&T)[4]) {
+  oz_pass<OP_CWT, false, NW>(oz_lds, gz, 0, [&](int t, int, int, const int64_t (&T)[4]) {
     #pragma unroll
     for (int v = 0; v < 4; ++v) Tt[t][v] = T[v];
   });
@@ -246,27 +249,28 @@ void k_oz_zfinal(OzArgs a) {
   const f2 kp{kh, (float)(kd - (double)kh)};
   double ek = 0.0;
   const float* kxy = a.kxy;
-  const float* c = a.c;
+  const int16_t* kxy_lo = oz_lo_plane(kxy, a.plane);
   float* out = a.out;
-  oz_pass<OP_CK, true, NW, false>(oz_lds, gz, 0, [&](int t, int k0, int o0, const int64_t (&T)[4]) {
-    // elements (x = o0 + 4 g + v, z = k0 + n)
-    const int64_t at = gp + (int64_t)(k0 + n) * zs + o0 + 4 * gq;
-    f2 kx[4];
-    oz_load4_cp(kxy, a.plane, at, kx);
-    const float4 ch4 = *reinterpret_cast<const float4*>(c + at);
-    const float4 cl4 = *reinterpret_cast<const float4*>(c + a.plane + at);
-    const float chv[4] = {ch4.x, ch4.y, ch4.z, ch4.w}, clv[4] = {cl4.x, cl4.y, cl4.z, cl4.w};
-    f2 o[4];
+  oz_pass<OP_CK, false, NW, false>(oz_lds, gz, 0, [&](int t, int k0, int o0, const int64_t (&T)[4]) {
+    // elements (z = k0 + 4 g + v, x = o0 + n)
+    const int x = o0 + n, z0 = k0 + 4 * gq;
+    // c there, from its digits (one word of four z per digit plane)
+    uint32_t dw[kOzDig];
+    #pragma unroll
+    for (int q = 0; q < kOzDig; ++q)
+      dw[q] = *reinterpret_cast<const uint32_t*>(oz_lds + q * gz.dstride + x * gz.pitch + z0);
     #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const f2 kc = oz_add(oz_tof(T[v], Ek), kx[v]);
-      ek = __builtin_fma((double)chv[v] + (double)clv[v], oz_pair_d(kc), ek);
+      const int64_t at = gp + (int64_t)(z0 + v) * zs + x;
+      const float khi = kxy[at];
+      const f2 kc = oz_add(oz_tof(T[v], Ek), f2{khi, oz_lo_of(khi, kxy_lo[at])});
+      ek = __builtin_fma(oz_tod(oz_undigits(dw, v), ec - 47), oz_pair_d(kc), ek);
       const f2 sc = pow2 ? f2{ksign * ldexpf(kc.hi, kx2 - 1), ksign * ldexpf(kc.lo, kx2 - 1)}
                          : oz_mul(kc, kp);
-      o[v] = oz_add(oz_tof(Tt[t][v], Et), sc);
+      const f2 o = oz_add(oz_tof(Tt[t][v], Et), sc);
+      out[at] = o.hi;
+      out[a.plane + at] = o.lo;
     }
-    *reinterpret_cast<float4*>(out + at) = make_float4(o[0].hi, o[1].hi, o[2].hi, o[3].hi);
-    *reinterpret_cast<float4*>(out + a.plane + at) = make_float4(o[0].lo, o[1].lo, o[2].lo, o[3].lo);
   });
   const double sk2 = oz_block_sum<NW>(ek);
   if (threadIdx.x == 0) a.ekin[(int64_t)b * a.m2 + y] = ks * sk2;
