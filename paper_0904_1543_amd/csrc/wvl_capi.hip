@@ -995,6 +995,7 @@ int hpsi_sequence(wvl_plan* p, hipStream_t st, const void* c, const double* V, d
       xa.ekin = kpl;
       xa.occupancy = p->xy_occ;
       xa.engine = p->xy_engine;
+      xa.rho_lds = 0;
       xa.order = nullptr;
       xa.perm = nullptr;
       xa.queue = nullptr;

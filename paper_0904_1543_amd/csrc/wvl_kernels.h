@@ -157,6 +157,8 @@ struct XyArgs {
   int32_t occupancy;     // waves per SIMD the kernel is compiled for (2 or 4)
   int32_t slot;          // shared: orbital g * G + slot of every group g; -1: all slots in turn
   int32_t engine;        // 0: vector FMA passes, 1: float64 matrix-core passes
+  int32_t rho_lds;       // shared, matrix engine, 2 waves per SIMD: the group's
+                         // density plane kept in LDS (set by launch_xy)
   // persistent launch of the unshared path (queue != nullptr): planes taken
   // from the queue in the order of `order` (prefix of planes over perm)
   const int32_t* order;

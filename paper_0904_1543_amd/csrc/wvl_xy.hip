@@ -1,6 +1,8 @@
 // Host dispatch of the in-plane kernel (the device code is in wvl_xy_impl.h,
 // instantiated per precision and engine by the wvl_xy_<form>.hip files).
 
+#include <stdlib.h>
+
 #include "wvl_plane.h"
 
 namespace wvl {
@@ -58,7 +60,12 @@ hipError_t launch_xy(int prec, const XyArgs& a, int m1, int m2, int nblocks, hip
   const size_t lds = xy_lds_bytes(prec, m1, m2, mx);
   if (mx) {
     const int mt = xy_tiles(m1, m2);
-    sh ? xy_launch_m<true>(a, mt, nblocks, lds, st) : xy_launch_m<false>(a, mt, nblocks, lds, st);
+    // one workgroup per CU anyway at 2 waves per SIMD: keep the group's
+    // density plane in LDS beside the plane (same pitch) when both fit
+    XyArgs b = a;
+    b.rho_lds = sh && a.occupancy == 2 && 2 * lds <= 160 * 1024 && !getenv("WVL_NO_RHO_LDS");
+    const size_t l = b.rho_lds ? 2 * lds : lds;
+    sh ? xy_launch_m<true>(b, mt, nblocks, l, st) : xy_launch_m<false>(b, mt, nblocks, l, st);
     return hipGetLastError();
   }
   const int mi = xy_items(m1, m2);

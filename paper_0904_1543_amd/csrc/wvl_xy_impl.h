@@ -426,7 +426,9 @@ __device__ __forceinline__ void eng_pass(typename E::V* buf, int m1, int m2, int
 }
 
 // One (orbital, plane): everything the kernel does for orbital b at plane z.
-template <int P, typename E, bool SHARED>
+// RL: the group's density plane is kept in LDS after the plane buffer (same
+// pitch) across the group's orbitals and written once by k_xy
+template <int P, typename E, bool SHARED, bool RL = false>
 __device__ __forceinline__ void xy_orbital_plane(const XyArgs& a, int b, int z, int g, int bi) {
   using T = Prec<P>;
   using V = typename T::V;
@@ -448,7 +450,8 @@ __device__ __forceinline__ void xy_orbital_plane(const XyArgs& a, int b, int z, 
   //      y = pot_scale V psi
   double ep = 0.0;
   const double* Vp = a.V + od.voff + (int64_t)z * npl;
-  double* rp = SHARED ? a.rho_part + (int64_t)g * a.M + (int64_t)z * npl : nullptr;
+  double* rp = SHARED && !RL ? a.rho_part + (int64_t)g * a.M + (int64_t)z * npl : nullptr;
+  double* rl = RL ? reinterpret_cast<double*>(buf + m2 * pitch) : nullptr;
   struct VR { double v, r; };
   plane_batched<kPlaneBatch>(
       m1, npl, pitch,
@@ -456,7 +459,8 @@ __device__ __forceinline__ void xy_orbital_plane(const XyArgs& a, int b, int z, 
       [&](int e, int pos, VR w) {
         const V psi = buf[pos];
         const double pd = T::d(psi);
-        if (SHARED && rp) rp[e] = bi == 0 ? od.occ * pd * pd : __builtin_fma(od.occ * pd, pd, w.r);
+        if (RL) rl[pos] = bi == 0 ? od.occ * pd * pd : __builtin_fma(od.occ * pd, pd, rl[pos]);
+        else if (SHARED && rp) rp[e] = bi == 0 ? od.occ * pd * pd : __builtin_fma(od.occ * pd, pd, w.r);
         ep = __builtin_fma(w.v * pd, pd, ep);
         buf[pos] = T::scale(psi, w.v * a.pot_scale);
       });
@@ -522,7 +526,7 @@ __device__ __forceinline__ void xy_orbital_plane(const XyArgs& a, int b, int z, 
 // (matrix-core engine, slot = -1); either way the group's density partial is
 // accumulated in orbital order.  Otherwise one (orbital, plane) per tile via
 // the plane prefix pq.
-template <int P, typename E, bool SHARED, int WPE>
+template <int P, typename E, bool SHARED, int WPE, bool RL = false>
 __global__ __launch_bounds__(kXyThreads) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
 void k_xy(XyArgs a) {
   if (SHARED) {
@@ -534,12 +538,21 @@ void k_xy(XyArgs a) {
       xy_orbital_plane<P, E, SHARED>(a, b, z, g, a.slot);
     } else {
       // every orbital of the group in turn: the group's density partial of
-      // this plane stays in L2 between them
+      // this plane stays in L2 between them (RL: in LDS, written once)
       #pragma nounroll
       for (int slot = 0; slot < a.G; ++slot) {
         const int b = g * a.G + slot;
         if (b >= a.norb) break;
-        xy_orbital_plane<P, E, SHARED>(a, b, z, g, slot);
+        xy_orbital_plane<P, E, SHARED, RL>(a, b, z, g, slot);
+      }
+      if (RL) {
+        __syncthreads();
+        extern __shared__ __align__(16) unsigned char xy_lds[];
+        const int m1 = a.orbs[g * a.G].m[0], m2 = a.orbs[g * a.G].m[1];
+        const int pitch = E::pitch(m1), npl = m1 * m2;
+        const double* rl = reinterpret_cast<const double*>(xy_lds) + m2 * pitch;
+        double* rp = a.rho_part + (int64_t)g * a.M + (int64_t)z * npl;
+        for (PtIter q(m1); q.e < npl; q.next()) rp[q.e] = rl[q.pos(pitch)];
       }
     }
   } else {
@@ -629,7 +642,9 @@ void xy_launch_e(const XyArgs& a, int nblocks, size_t lds, hipStream_t st) {
   // occupancy target: 4 waves per SIMD (two workgroups per CU, <= 128
   // registers) or 2 (one workgroup per CU, <= 256 registers)
   const dim3 g(nblocks), b(kXyThreads);
-  if (a.occupancy == 2) hipLaunchKernelGGL((k_xy<P, E, SH, 2>), g, b, lds, st, a);
+  if (a.occupancy == 2 && a.rho_lds)
+    hipLaunchKernelGGL((k_xy<P, E, SH, 2, E::kGroupLoop && SH>), g, b, lds, st, a);
+  else if (a.occupancy == 2) hipLaunchKernelGGL((k_xy<P, E, SH, 2>), g, b, lds, st, a);
   else hipLaunchKernelGGL((k_xy<P, E, SH, 4>), g, b, lds, st, a);
 }
 
