@@ -235,7 +235,11 @@ int wvl_energy_gradient(wvl_plan *plan, const void *c, const double *V, double g
  *         kinetic filter and analysis composed, Sec. 2.4 last paragraph and
  *         Sec. 6.1: the fused wavelet + kinetic kernel), with both in-plane
  *         axes applied by one plane-resident kernel when the plane fits it
- *         (periodic plans), else one pass per axis; WVL_PRECOND_PASSES: the
+ *         (periodic plans), else one pass per axis; WVL_F32C plans that the
+ *         exact digit-product engine covers (uniform, fine lengths multiples
+ *         of 16, equal spacing on all axes; no shared potential needed) run
+ *         that form with exact int8 products (WVL_Q_PRECOND_FORM tells which
+ *         form a plan takes); WVL_PRECOND_PASSES: the
  *         combined filter, one pass per axis; WVL_PRECOND_SEPARATE: the
  *         separate 3D synthesis, kinetic (with K_0) and analysis passes of
  *         the paper's GPU design (Sec. 2.4, Sec. 3.4)
@@ -322,7 +326,12 @@ int wvl_plan_tuning(const wvl_plan *plan, int32_t *variant, double *times_ms, in
  *   WVL_Q_PGRID       workgroups per CU of the persistent pass launches
  *   WVL_Q_TUNE_BEST   tuner candidate kept (index into times_ms), -1 untuned
  *   WVL_Q_FUSED_Z     1 if the last z step runs as one fused launch (it does
- *                     not when hpsi is c; see wvl_local_hpsi) */
+ *                     not when hpsi is c; see wvl_local_hpsi)
+ *   WVL_Q_PRECOND_FORM operator of wvl_precondition's default mode: 0 one
+ *                     combined-filter pass per axis, 1 z pass + plane-resident
+ *                     in-plane kernel, 2 the same with the exact digit
+ *                     products (WVL_F32C uniform periodic plans, fine lengths
+ *                     multiples of 16, equal spacing on all axes) */
 #define WVL_Q_VARIANT 0
 #define WVL_Q_GROUP 1
 #define WVL_Q_PERSISTENT 2
@@ -330,6 +339,7 @@ int wvl_plan_tuning(const wvl_plan *plan, int32_t *variant, double *times_ms, in
 #define WVL_Q_PGRID 4
 #define WVL_Q_TUNE_BEST 5
 #define WVL_Q_FUSED_Z 6
+#define WVL_Q_PRECOND_FORM 7
 int wvl_plan_query(const wvl_plan *plan, int32_t what, int64_t *value);
 
 /* Launch profiling: with capacity > 0, every kernel launch of the following

@@ -111,6 +111,7 @@ struct wvl_plan {
   // exact-product engine of the compensated form (uniform batches with a
   // shared potential, lengths multiples of 16, isotropic grid spacing)
   bool oz_ok = false, use_oz = false;
+  bool oz_pc = false;   // the preconditioner's operator with the exact products (no potential needed)
   int oz_occ_xy = 2, oz_occ_z = 4;   // waves per SIMD of the plane and final kernels
   std::vector<int32_t> pxz;          // prefix of xz-planes (m2 per orbital)
   int32_t* d_pxz = nullptr;
@@ -461,13 +462,15 @@ int wvl_plan_create(wvl_ctx* ctx, const wvl_orbital* orbs, int32_t norb, int32_t
   }
   // exact-product engine of the compensated form
   {
-    bool ok = prec == WVL_F32C && p->shared && !p->bc_any && !getenv("WVL_F32C_VECTOR") &&
+    bool ok = prec == WVL_F32C && uniform && !p->bc_any && !getenv("WVL_F32C_VECTOR") &&
               !getenv("WVL_NO_PLANE_KERNEL");
     if (ok) ok = oz_supported(p->orbs[0].m[0], p->orbs[0].m[1], p->orbs[0].m[2]);
     for (int b = 0; ok && b < norb; ++b) {
       const double* k = p->orbs[b].kscale;
       ok = k[0] == k[1] && k[1] == k[2];
     }
+    p->oz_pc = ok;
+    ok = ok && p->shared;
     p->oz_ok = ok;
     p->use_oz = ok;
     if (ok) p->variant = 3;
@@ -535,7 +538,7 @@ int wvl_plan_create(wvl_ctx* ctx, const wvl_orbital* orbs, int32_t norb, int32_t
     p->o_Li = off; off += align256(sizeof(double) * (size_t)norb * norb);
     p->o_T = off; off += align256(sizeof(double) * (size_t)norb * norb);
   }
-  if (p->xy_ok || p->oz_ok) {   // the plane path may be chosen later by the tuner
+  if (p->xy_ok || p->oz_pc) {   // the plane path may be chosen later by the tuner
     if (p->shared) {
       p->o_rhop = off;
       off += align256(sizeof(double) * (size_t)p->xy_ngroups * p->M);
@@ -543,9 +546,11 @@ int wvl_plan_create(wvl_ctx* ctx, const wvl_orbital* orbs, int32_t norb, int32_t
     p->o_epl = off; off += align256(sizeof(double) * (size_t)p->pq[norb]);
     p->o_kpl = off; off += align256(sizeof(double) * (size_t)p->pq[norb]);
   }
-  if (p->oz_ok) {   // potential as float pairs, plane exponents, per-xz-plane e_kin
+  if (p->oz_ok) {   // potential as float pairs, plane exponents
     p->o_ozv = off; off += align256(sizeof(float) * 2 * (size_t)p->M);
     p->o_oze = off; off += align256(sizeof(int) * (size_t)p->orbs[0].m[2]);
+  }
+  if (p->oz_pc) {   // per-xz-plane kinetic sums
     p->o_kpl2 = off; off += align256(sizeof(double) * (size_t)p->pxz[norb]);
   }
   p->o_queue = off; off += align256(sizeof(int32_t) * kQueueCounters);   // work-queue counters
@@ -1340,6 +1345,19 @@ int wvl_energy_gradient(wvl_plan* p, const void* c, const double* V, double g_lo
   return WVL_OK;
 }
 
+// Operator form of the preconditioner's fused (combined-filter) step:
+//   0 one combined-filter pass per axis;
+//   1 the plane-resident form: z pass, then both in-plane passes with the
+//     plane of p in LDS (periodic plans whose planes fit the in-plane kernel);
+//   2 the same two launches with the exact digit products (compensated
+//     uniform periodic plans that the engine covers).
+static int precond_form(const wvl_plan* p, uint32_t mode) {
+  if ((mode & (WVL_PRECOND_SEPARATE | WVL_PRECOND_PASSES)) || p->bc_any) return 0;
+  if (p->oz_pc) return 2;
+  const bool mx = xy_matrix_engine(p->prec, p->xy_m1, p->xy_m2) && !getenv("WVL_XY_VECTOR");
+  return p->xy_ok && xy_supported(p->prec, p->xy_m1, p->xy_m2, mx) ? 1 : 0;
+}
+
 int wvl_precondition(wvl_plan* p, const void* g, const double* eps, int32_t iters, uint32_t mode,
                      void* gt, double* res, void* ws, void* stream) {
   if (int r = check_plan(p)) return r;
@@ -1376,18 +1394,37 @@ int wvl_precondition(wvl_plan* p, const void* g, const double* eps, int32_t iter
   const int nt = p->pc[p->norb];
   const int64_t plane = p->elems;
   const bool separate = (mode & WVL_PRECOND_SEPARATE) != 0;
-  // the plane-resident form: z pass, then both in-plane passes with the plane
-  // of p in LDS (periodic plans whose planes fit the in-plane kernel)
   const bool helm_mx = xy_matrix_engine(p->prec, p->xy_m1, p->xy_m2) && !getenv("WVL_XY_VECTOR");
-  const bool plane_form = !separate && !(mode & WVL_PRECOND_PASSES) && !p->bc_any && p->xy_ok &&
-                          xy_supported(p->prec, p->xy_m1, p->xy_m2, helm_mx);
-  double* kpl = plane_form ? (double*)wsp(ws, p->o_kpl) : nullptr;
+  const int form = precond_form(p, mode);
+  const bool exact = form == 2, plane_form = form == 1;
+  double* kpl = plane_form || exact ? (double*)wsp(ws, p->o_kpl) : nullptr;
+  OzHelmArgs oa{};
+  if (exact) {
+    const OzLds l = oz_lds(p->orbs[0].m[0], p->orbs[0].m[1], p->orbs[0].m[2]);
+    oa.orbs = p->d_orbs;
+    oa.norb = p->norb;
+    oa.m1 = p->orbs[0].m[0];
+    oa.m2 = p->orbs[0].m[1];
+    oa.m3 = p->orbs[0].m[2];
+    oa.p = (const float*)Pv;
+    oa.q = (float*)Q;
+    oa.plane = plane;
+    oa.ez = (double*)wsp(ws, p->o_kpl2);
+    oa.exy = kpl;
+    oa.dxy = l.dxy;
+    oa.dz = l.dz;
+  }
   WVL_HIP(hipMemcpyAsync(eps_d, eps, sizeof(double) * p->norb, hipMemcpyHostToDevice, st));
   WVL_CHK(launch_cg_init(p->prec, gp, nt, g, gt, R, Pv, eps_d, plane, prz, ppp, prr, st));
   for (int it = 0; it < iters; ++it) {
     // q = (A Kin S - eps) p, with the kinetic energy partials p.Kin p
     if (p->bc_any) {
       if (int r = bc_kinetic(p, st, Pv, nullptr, plane, Q, plane, Q, plane, 1.0, ez, ey, ex)) return r;
+    } else if (exact) {
+      // the same with the exact digit products: k K_z p over xz-planes,
+      // then k (K_x + K_y) p added plane by plane
+      Mark mk(p, st, ST_HELM);
+      WVL_CHK(launch_oz_helm(oa, st));
     } else if (plane_form) {
       // K_z p by the z pass, then (K_x + K_y) p added plane by plane
       WVL_CHK(q.pass(OP_CK, 3, Pv, Q, nullptr, 1.0, ez));
@@ -1415,6 +1452,9 @@ int wvl_precondition(wvl_plan* p, const void* g, const double* eps, int32_t iter
       if (p->bc_any)
         WVL_CHK(launch_cg_alpha(p->norb, p->d_pb + 2 * (p->norb + 1), p->d_pb + (p->norb + 1), p->d_pb,
                                 p->d_pc, ez, ey, ex, prz, ppp, eps_d, sc, st));
+      else if (exact)
+        WVL_CHK(launch_cg_alpha(p->norb, p->d_pxz, p->d_pq, nullptr, p->d_pc, oa.ez, kpl, nullptr,
+                                prz, ppp, eps_d, sc, st));
       else if (plane_form)
         WVL_CHK(launch_cg_alpha(p->norb, p->d_pz, p->d_pq, nullptr, p->d_pc, ez, kpl, nullptr, prz,
                                 ppp, eps_d, sc, st));
@@ -1568,6 +1608,7 @@ int wvl_plan_query(const wvl_plan* p, int32_t what, int64_t* value) {
     case WVL_Q_PGRID: *value = p->pgrid_mul; break;
     case WVL_Q_TUNE_BEST: *value = p->tune_best; break;
     case WVL_Q_FUSED_Z: *value = p->use_xy && p->zfuse ? 1 : 0; break;
+    case WVL_Q_PRECOND_FORM: *value = precond_form(p, 0); break;
     default: return fail(WVL_EINVAL, "unknown query %d", what);
   }
   return WVL_OK;

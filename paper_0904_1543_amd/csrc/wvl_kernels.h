@@ -209,6 +209,19 @@ struct OzArgs {
   double* ekin;          // per (orbital, y) at b * m2 + y: <c, k (K_x + K_y + K_z) c>
   int32_t dxy, dz;       // digit-plane strides (bytes) of the xy and xz kernels
 };
+// The preconditioner's operator with the exact products (same batches
+// without the potential): q = k K p, e per xz-plane (K_z) and per z-plane.
+struct OzHelmArgs {
+  const OrbDev* orbs;
+  int32_t norb, m1, m2, m3;
+  const float* p;
+  float* q;
+  int64_t plane;
+  double* ez;            // <p, k K_z p> per (orbital, y) at b * m2 + y
+  double* exy;           // <p, k (K_x + K_y) p> per (orbital, z) at b * m3 + z
+  int32_t dxy, dz;
+};
+hipError_t launch_oz_helm(const OzHelmArgs& a, hipStream_t st);
 struct OzLds { int dxy, dz; size_t xy_bytes, z_bytes; };
 OzLds oz_lds(int m1, int m2, int m3);
 bool oz_supported(int m1, int m2, int m3);

@@ -276,7 +276,121 @@ void k_oz_zfinal(OzArgs a) {
   if (threadIdx.x == 0) a.ekin[(int64_t)b * a.m2 + y] = ks * sk2;
 }
 
+// ---------------------------------------------------------------------------
+// The preconditioner's operator (Sec. 2, Eq. "precon", the shift applied by
+// the CG update): q = k (K_x + K_y + K_z) p for the compensated form, with
+// <p, q> per plane for the step length.
+//   z:  q = k K_z p over xz-planes, <p, k K_z p> per xz-plane
+//   xy: q += k (K_x + K_y) p over z-planes, <p, k (K_x + K_y) p> per plane
+// k = -1/(2 h^2) multiplies the exact sums (a power of two: exact scaling).
+
+__device__ __forceinline__ f2 oz_kscale(f2 r, bool pow2, int kx2, float ksign, f2 kp) {
+  return pow2 ? f2{ksign * ldexpf(r.hi, kx2 - 1), ksign * ldexpf(r.lo, kx2 - 1)} : oz_mul(r, kp);
+}
+
+__global__ __launch_bounds__(64 * kOzZWaves) __attribute__((amdgpu_waves_per_eu(4, 4)))
+void k_oz_helm_z(OzHelmArgs a) {
+  extern __shared__ __align__(16) uint8_t oz_lds[];
+  constexpr int NW = kOzZWaves;
+  const int b = blockIdx.x / a.m2, y = blockIdx.x - b * a.m2;
+  const int m1 = a.m1, m3 = a.m3;
+  const int64_t zs = (int64_t)m1 * a.m2;
+  const OrbDev& od = a.orbs[b];
+  const int64_t gp = od.off + (int64_t)y * m1;
+  const OzGeo gz{m3, m1, oz_pitch(m3), a.dz};
+  const int lane = threadIdx.x & 63, n = lane & 15, gq = lane >> 4;
+  const int ep = oz_load<false, NW>(a.p, a.plane, gp, zs, gz, oz_lds, -2000);
+  __syncthreads();
+  const int Ek = ep + OzK<OP_CK>::EF - 54;
+  const double kd = od.kscale[0];
+  int kx2 = 0;
+  const double kf = frexp(kd, &kx2);
+  const bool pow2 = kf == 0.5 || kf == -0.5;
+  const float ksign = kf < 0 ? -1.0f : 1.0f;
+  const float kh = (float)kd;
+  const f2 kp{kh, (float)(kd - (double)kh)};
+  double e = 0.0;
+  float* q = a.q;
+  oz_pass<OP_CK, false, NW, false>(oz_lds, gz, 0, [&](int, int k0, int o0, const int64_t (&T)[4]) {
+    // elements (z = k0 + 4 g + v, x = o0 + n); p there from its digits
+    const int x = o0 + n, z0 = k0 + 4 * gq;
+    uint32_t dw[kOzDig];
+    #pragma unroll
+    for (int d = 0; d < kOzDig; ++d)
+      dw[d] = *reinterpret_cast<const uint32_t*>(oz_lds + d * gz.dstride + x * gz.pitch + z0);
+    #pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const f2 r = oz_tof(T[v], Ek);
+      e = __builtin_fma(oz_tod(oz_undigits(dw, v), ep - 47), oz_pair_d(r), e);
+      const f2 o = oz_kscale(r, pow2, kx2, ksign, kp);
+      const int64_t at = gp + (int64_t)(z0 + v) * zs + x;
+      q[at] = o.hi;
+      q[a.plane + at] = o.lo;
+    }
+  });
+  const double sk = oz_block_sum<NW>(e);
+  if (threadIdx.x == 0) a.ez[(int64_t)b * a.m2 + y] = kd * sk;
+}
+
+template <int NW>
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW == 8 ? 4 : 3, NW == 8 ? 4 : 3)))
+void k_oz_helm_xy(OzHelmArgs a) {
+  extern __shared__ __align__(16) uint8_t oz_lds[];
+  const int b = blockIdx.x / a.m3, z = blockIdx.x - b * a.m3;
+  const int m1 = a.m1, m2 = a.m2;
+  const OzGeo gx{m1, m2, oz_pitch(m1), a.dxy};
+  const OzGeo gy{m2, m1, oz_pitch(m2), a.dxy};
+  const OrbDev& od = a.orbs[b];
+  const int64_t gp = od.off + (int64_t)z * m1 * m2;
+  const int lane = threadIdx.x & 63, n = lane & 15, gq = lane >> 4;
+  const int ep = oz_load<true, NW>(a.p, a.plane, gp, m1, gx, oz_lds, -2000);
+  __syncthreads();
+  int64_t Tx[oz_mt(NW)][4];
+  oz_pass<OP_CK, true, NW, false>(oz_lds, gx, 1, [&](int t, int, int, const int64_t (&T)[4]) {
+    #pragma unroll
+    for (int v = 0; v < 4; ++v) Tx[t][v] = T[v];
+  });
+  oz_transpose<NW>(oz_lds, gx, gy);
+  const int Ek = ep + OzK<OP_CK>::EF - 54;
+  const double kd = od.kscale[0];
+  int kx2 = 0;
+  const double kf = frexp(kd, &kx2);
+  const bool pow2 = kf == 0.5 || kf == -0.5;
+  const float ksign = kf < 0 ? -1.0f : 1.0f;
+  const float kh = (float)kd;
+  const f2 kp{kh, (float)(kd - (double)kh)};
+  double e = 0.0;
+  float* q = a.q;
+  oz_pass<OP_CK, false, NW, false>(oz_lds, gy, 2, [&](int t, int k0, int o0, const int64_t (&T)[4]) {
+    // elements (y = k0 + 4 g + v, x = o0 + n); p there from its digits ([x][y])
+    const int x = o0 + n, y0 = k0 + 4 * gq;
+    uint32_t dw[kOzDig];
+    #pragma unroll
+    for (int d = 0; d < kOzDig; ++d)
+      dw[d] = *reinterpret_cast<const uint32_t*>(oz_lds + d * gy.dstride + x * gy.pitch + y0);
+    #pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const f2 r = oz_tof(T[v] + Tx[t][v], Ek);
+      e = __builtin_fma(oz_tod(oz_undigits(dw, v), ep - 47), oz_pair_d(r), e);
+      const int64_t at = gp + (int64_t)(y0 + v) * m1 + x;
+      const f2 o = oz_add(f2{q[at], q[a.plane + at]}, oz_kscale(r, pow2, kx2, ksign, kp));
+      q[at] = o.hi;
+      q[a.plane + at] = o.lo;
+    }
+  });
+  const double sk = oz_block_sum<NW>(e);
+  if (threadIdx.x == 0) a.exy[(int64_t)b * a.m3 + z] = kd * sk;
+}
+
 }  // namespace
+
+hipError_t launch_oz_helm(const OzHelmArgs& a, hipStream_t st) {
+  const OzLds l = oz_lds(a.m1, a.m2, a.m3);
+  hipLaunchKernelGGL(k_oz_helm_z, dim3(a.norb * a.m2), dim3(64 * kOzZWaves), l.z_bytes, st, a);
+  const size_t xy = (size_t)kOzDig * l.dxy;       // digits only (no density plane)
+  hipLaunchKernelGGL(k_oz_helm_xy<kOzZWaves>, dim3(a.norb * a.m3), dim3(64 * kOzZWaves), xy, st, a);
+  return hipGetLastError();
+}
 
 // ---------------------------------------------------------------------------
 // host side

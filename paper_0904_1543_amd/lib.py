@@ -22,7 +22,7 @@ WVL_F64, WVL_F32, WVL_F32C = 0, 1, 2
 WVL_SHARED_V, WVL_USE_GRAPH, WVL_PERSISTENT, WVL_AUTOTUNE = 1, 2, 4, 8
 WVL_FREE_BC, WVL_SURFACE_BC = 16, 32
 (WVL_Q_VARIANT, WVL_Q_GROUP, WVL_Q_PERSISTENT, WVL_Q_XDIV, WVL_Q_PGRID, WVL_Q_TUNE_BEST,
- WVL_Q_FUSED_Z) = range(7)
+ WVL_Q_FUSED_Z, WVL_Q_PRECOND_FORM) = range(8)
 WVL_PRECOND_SEPARATE, WVL_PRECOND_PASSES = 1, 2
 
 STATUS_NAMES = {0: "WVL_OK", -1: "WVL_EINVAL", -2: "WVL_EUNSUPPORTED", -3: "WVL_ENOMEM",

@@ -296,3 +296,29 @@ def test_exact_product_engine_selection(dry, monkeypatch):
     monkeypatch.delenv("WVL_F32C_VECTOR")
     monkeypatch.setenv("WVL_NO_PLANE_KERNEL", "1")
     assert variant([(48, 48, 48)] * 4) == 0
+
+
+def test_precondition_form_selection(dry, monkeypatch):
+    """The preconditioner's default operator form: exact digit products for
+    compensated plans the engine covers (a shared potential is not needed),
+    the plane-resident vector form for other planes that fit, else passes."""
+    q = lib.raw("wvl_plan_query")
+    v = ctypes.c_int64()
+
+    def form(dims, prec=2, flags=1, **kw):
+        rc, p = _plan(dry, dims, prec=prec, flags=flags, **kw)
+        assert rc == lib.WVL_OK
+        assert q(p, lib.WVL_Q_PRECOND_FORM, ctypes.byref(v)) == lib.WVL_OK
+        lib.wvl_plan_destroy(p)
+        return v.value
+
+    assert form([(48, 48, 48)] * 4) == 2
+    assert form([(48, 48, 48)] * 2, flags=0) == 2            # one potential per orbital
+    assert form([(8, 24, 16)] * 3, hgrid=(0.8, 0.8, 0.8)) == 2
+    assert form([(16, 16, 16)] * 2, hgrid=(1.0, 0.9, 1.0)) == 1
+    assert form([(20, 18, 17)] * 2) == 1                     # lengths not multiples of 16
+    assert form([(48, 48, 48)] * 4, prec=0) == 1
+    assert form([(16, 16, 16)] * 2, flags=1 | lib.WVL_FREE_BC) == 0
+    monkeypatch.setenv("WVL_F32C_VECTOR", "1")
+    assert form([(48, 48, 48)] * 4) == 1
+    monkeypatch.delenv("WVL_F32C_VECTOR")

@@ -9,12 +9,20 @@ G > 1 with a ragged last group, anisotropic spacing (falls back to the vector
 engine), the two scale factors, in place, an all-zero orbital and orbitals
 scaled by 1e-20 and 1e15 (each plane takes its own exponent).  Every result
 is held to 1e-10 normwise and elementwise (Sec. 2.4 steps 2-6, Sec. 2.5).
+
+The preconditioner's operator (Sec. 2, Eq. "precon") runs on the same engine
+for compensated uniform batches of those lengths and spacings, with or
+without a shared potential: CG steps against the oracle's, with spacings
+whose kinetic factor -1/(2 h^2) is a power of two (h = 1, exact scaling of
+the pairs) or not (h = 0.8), orbitals of very different magnitudes and a
+zero one.
 """
 
 import numpy as np
 import pytest
 import torch
 
+from oracle import precond as PC
 from oracle import wavelet as W
 from paper_0904_1543_amd import inputs, lib, ops
 from parity_helpers import assert_close, assert_scalar
@@ -134,3 +142,56 @@ def test_exact_engine_is_deterministic_and_graph_replays():
         rg = gplan.local_hpsi(c, V)
         torch.cuda.synchronize()
         assert torch.equal(rg["hpsi"], r1["hpsi"]) and torch.equal(rg["energies"], r1["energies"])
+
+
+PC_CASES = {"one_tile": (2, (8, 8, 8)), "nonsquare": (3, (16, 24, 8)), "tall": (2, (24, 16, 32))}
+
+
+def _pc_run(plan, C, eps, iters, hg):
+    assert plan.query(lib.WVL_Q_PRECOND_FORM) == 2
+    gt, res = plan.precondition(plan.pack(C), eps, iters, residuals=True)
+    ref = [PC.pcg(g, e, iters, hg) for g, e in zip(C, eps)]
+    return plan.unpack(gt), res.cpu().numpy(), ref
+
+
+@pytest.mark.parametrize("h", [1.0, 0.8])
+@pytest.mark.parametrize("case", list(PC_CASES))
+def test_exact_preconditioner_against_oracle(case, h):
+    norb, dims = PC_CASES[case]
+    cs = inputs.random_case(170 + norb, norb, dims)
+    eps = -inputs.rng_for(11).uniform(0.1, 1.0, size=norb)
+    hg = (h, h, h)
+    plan = ops.Plan(cs["dims"], prec="f32c", hgrid=hg)
+    got, res, ref = _pc_run(plan, cs["C"], eps, 4, hg)
+    assert_close(got, [r[0] for r in ref], TOL, "preconditioned gradient")
+    assert_close(res, np.array([r[1] for r in ref]), TOL, "residual norms")
+
+
+def test_exact_preconditioner_per_orbital_potential_and_magnitudes():
+    """Orbitals scaled by 1e-20 and 1e15 and a zero one, in a plan without a
+    shared potential: each plane of p takes its own exponent."""
+    cs = inputs.random_case(175, 4, (8, 16, 8))
+    C = cs["C"].copy()
+    C[0] *= 1e-20
+    C[1] *= 1e15
+    C[2] = 0.0
+    eps = -inputs.rng_for(12).uniform(0.1, 1.0, size=4)
+    plan = ops.Plan(cs["dims"], prec="f32c", shared_v=False)
+    got, res, ref = _pc_run(plan, C, eps, 6, (1.0, 1.0, 1.0))
+    for b in (0, 1, 3):
+        assert_close(got[b], ref[b][0], TOL, f"orbital {b}")
+        assert_scalar(res[b], ref[b][1], TOL, f"residual {b}")
+    assert not np.any(got[2]) and res[2] == 0.0
+
+
+def test_exact_preconditioner_matches_vector_form(monkeypatch):
+    """Both compensated forms solve the same recurrence to 1e-10."""
+    cs = inputs.random_case(176, 3, (16, 8, 16))
+    eps = -inputs.rng_for(13).uniform(0.1, 1.0, size=3)
+    plan = ops.Plan(cs["dims"], prec="f32c")
+    a = plan.precondition(plan.pack(cs["C"]), eps, 8)
+    monkeypatch.setenv("WVL_F32C_VECTOR", "1")
+    vplan = ops.Plan(cs["dims"], prec="f32c")
+    assert vplan.query(lib.WVL_Q_PRECOND_FORM) == 1
+    b = vplan.precondition(vplan.pack(cs["C"]), eps, 8)
+    assert_close(plan.unpack(a), plan.unpack(b), TOL, "exact vs vector form")
