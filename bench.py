@@ -248,6 +248,9 @@ def errors_vs_oracle(got, energies, ref):
 
 
 PRECOND_ITERS = 5
+PRECOND_FORMS = {0: "combined filter, one pass per axis",
+                 1: "z pass + plane-resident in-plane kernel",
+                 2: "z pass + plane-resident in-plane kernel, exact int8 digit products"}
 
 
 def run_precond(C, dims, steps, warmup, check):
@@ -259,7 +262,7 @@ def run_precond(C, dims, steps, warmup, check):
     paper's GPU design.  Inputs: the batch's coefficients as gradients, one
     orbital energy per orbital uniform in [-1, -0.1]."""
     import torch
-    from paper_0904_1543_amd import inputs, ops
+    from paper_0904_1543_amd import inputs, lib, ops
 
     norb = len(dims)
     pts = norb * int(np.prod(inputs.fine_shape(dims[0])))
@@ -291,6 +294,8 @@ def run_precond(C, dims, steps, warmup, check):
             ms = t0.elapsed_time(t1) / steps
             rec = {"ms_per_call": ms, "ms_per_cg_step": ms / PRECOND_ITERS,
                    "orbital_gridpoints_per_s_per_step": pts / (ms / PRECOND_ITERS * 1e-3)}
+            if form is None:
+                rec["operator"] = PRECOND_FORMS[plan.query(lib.WVL_Q_PRECOND_FORM)]
             if refs is not None:
                 got = plan.to_f64(gt)
                 M = plan.M[0]

@@ -26,8 +26,10 @@
  * Memory.  Every data pointer is a DEVICE pointer owned by the caller; the
  * library neither frees nor keeps it after the call returns (except the graph
  * cache of WVL_USE_GRAPH, which records pointers and re-records when they
- * change).  `ws` is caller-owned device workspace of wvl_plan_workspace()
- * bytes (256-byte aligned).  `stream` is a hipStream_t (NULL = default stream).
+ * change).  Batch arrays start on a 16-byte boundary (WVL_EINVAL otherwise;
+ * hipMalloc and torch allocations are).  `ws` is caller-owned device
+ * workspace of wvl_plan_workspace() bytes (256-byte aligned).  `stream` is a
+ * hipStream_t (NULL = default stream).
  *
  * Errors.  Every call returns a wvl_status.  Arguments are checked before any
  * HIP call is made; HIP failures map to WVL_EHIP.  Calls are asynchronous on

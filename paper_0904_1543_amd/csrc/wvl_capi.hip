@@ -11,6 +11,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <initializer_list>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -245,6 +246,15 @@ static size_t batch_bytes(const wvl_plan* p) {
 static bool overlap(const void* a, size_t na, const void* b, size_t nb) {
   const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
   return x < y + nb && y < x + na;
+}
+
+// batch arrays start on a 16-byte boundary (the kernels move four elements
+// of a plane per access); nullptrs are checked elsewhere
+static int check_aligned(const char* what, std::initializer_list<const void*> ptrs) {
+  for (const void* q : ptrs)
+    if (((uintptr_t)q & 15) != 0)
+      return fail(WVL_EINVAL, "%s: batch array %p is not 16-byte aligned", what, q);
+  return WVL_OK;
 }
 
 // input and output batch arrays of an operation must not share memory
@@ -1197,6 +1207,7 @@ extern "C" {
 int wvl_synthesis(wvl_plan* p, const void* c, void* s, void* ws, void* stream) {
   if (int r = check_plan(p)) return r;
   if (!c || !s || !ws) return fail(WVL_EINVAL, "wvl_synthesis: NULL pointer");
+  if (int r = check_aligned("wvl_synthesis", {c, s})) return r;
   if (int r = check_disjoint(p, c, s, "wvl_synthesis")) return r;
   if (int r = check_periodic(p, "wvl_synthesis")) return r;
   if (int r = check_gpu(p)) return r;
@@ -1208,6 +1219,7 @@ int wvl_synthesis(wvl_plan* p, const void* c, void* s, void* ws, void* stream) {
 int wvl_analysis(wvl_plan* p, const void* s, void* c, void* ws, void* stream) {
   if (int r = check_plan(p)) return r;
   if (!c || !s || !ws) return fail(WVL_EINVAL, "wvl_analysis: NULL pointer");
+  if (int r = check_aligned("wvl_analysis", {c, s})) return r;
   if (int r = check_disjoint(p, s, c, "wvl_analysis")) return r;
   if (int r = check_periodic(p, "wvl_analysis")) return r;
   if (int r = check_gpu(p)) return r;
@@ -1220,6 +1232,7 @@ int wvl_magic_filter(wvl_plan* p, const void* in, void* out, int transpose, void
                      void* stream) {
   if (int r = check_plan(p)) return r;
   if (!in || !out || !ws) return fail(WVL_EINVAL, "wvl_magic_filter: NULL pointer");
+  if (int r = check_aligned("wvl_magic_filter", {in, out})) return r;
   if (int r = check_disjoint(p, in, out, "wvl_magic_filter")) return r;
   if (int r = check_periodic(p, "wvl_magic_filter")) return r;
   if (int r = check_gpu(p)) return r;
@@ -1231,6 +1244,7 @@ int wvl_magic_filter(wvl_plan* p, const void* in, void* out, int transpose, void
 int wvl_kinetic(wvl_plan* p, const void* s, const void* k0, void* out, void* ws, void* stream) {
   if (int r = check_plan(p)) return r;
   if (!s || !out || !ws) return fail(WVL_EINVAL, "wvl_kinetic: NULL pointer");
+  if (int r = check_aligned("wvl_kinetic", {s, k0, out})) return r;
   if (int r = check_disjoint(p, s, out, "wvl_kinetic")) return r;
   if (int r = check_periodic(p, "wvl_kinetic")) return r;
   if (k0 && overlap(k0, batch_bytes(p), s, batch_bytes(p)))
@@ -1249,6 +1263,7 @@ int wvl_local_density(wvl_plan* p, const void* c, double* rho, int accumulate, v
                       void* stream) {
   if (int r = check_plan(p)) return r;
   if (!c || !rho || !ws) return fail(WVL_EINVAL, "wvl_local_density: NULL pointer");
+  if (int r = check_aligned("wvl_local_density", {c})) return r;
   if (!p->shared) return fail(WVL_EUNSUPPORTED, "wvl_local_density needs a WVL_SHARED_V plan");
   if (int r = check_gpu(p)) return r;
   hipStream_t st = (hipStream_t)stream;
@@ -1277,6 +1292,7 @@ int wvl_local_hpsi(wvl_plan* p, const void* c, const double* V, double pot_scale
                    double* e_orb, void* ws, void* stream) {
   if (int r = check_plan(p)) return r;
   if (!c || !V || !hpsi || !ws) return fail(WVL_EINVAL, "wvl_local_hpsi: NULL pointer");
+  if (int r = check_aligned("wvl_local_hpsi", {c, hpsi})) return r;
   if (rho && !p->shared) return fail(WVL_EUNSUPPORTED, "rho needs a WVL_SHARED_V plan");
   if (!isfinite(pot_scale) || !isfinite(kin_scale))
     return fail(WVL_EINVAL, "wvl_local_hpsi: scales must be finite");
@@ -1324,6 +1340,7 @@ int wvl_energy_gradient(wvl_plan* p, const void* c, const double* V, double g_lo
                         void* grad, void* ws, void* stream) {
   if (int r = check_plan(p)) return r;
   if (!c || !V || !grad || !ws) return fail(WVL_EINVAL, "wvl_energy_gradient: NULL pointer");
+  if (int r = check_aligned("wvl_energy_gradient", {c, grad})) return r;
   if (!isfinite(g_loc) || !isfinite(g_kin))
     return fail(WVL_EINVAL, "wvl_energy_gradient: weights must be finite");
   if (grad != c && overlap(c, batch_bytes(p), grad, batch_bytes(p)))
@@ -1362,6 +1379,7 @@ int wvl_precondition(wvl_plan* p, const void* g, const double* eps, int32_t iter
                      void* gt, double* res, void* ws, void* stream) {
   if (int r = check_plan(p)) return r;
   if (!g || !eps || !gt || !ws) return fail(WVL_EINVAL, "wvl_precondition: NULL pointer");
+  if (int r = check_aligned("wvl_precondition", {g, gt})) return r;
   if (iters < 0 || iters > 10000) return fail(WVL_EINVAL, "wvl_precondition: iters = %d", iters);
   if (mode & ~(uint32_t)(WVL_PRECOND_SEPARATE | WVL_PRECOND_PASSES))
     return fail(WVL_EINVAL, "wvl_precondition: unknown mode bits 0x%x", mode);
@@ -1549,6 +1567,7 @@ static size_t cbatch_bytes(const wvl_plan* p) {
 int wvl_decompress(wvl_plan* p, const void* psi_c, void* c, void* stream) {
   if (int r = check_plan(p)) return r;
   if (!psi_c || !c) return fail(WVL_EINVAL, "wvl_decompress: NULL pointer");
+  if (int r = check_aligned("wvl_decompress", {c})) return r;
   if (int r = check_compressed(p, "wvl_decompress")) return r;
   if (overlap(psi_c, cbatch_bytes(p), c, batch_bytes(p)))
     return fail(WVL_EINVAL, "wvl_decompress: output overlaps input");
@@ -1562,6 +1581,7 @@ int wvl_decompress(wvl_plan* p, const void* psi_c, void* c, void* stream) {
 int wvl_compress(wvl_plan* p, const void* c, void* psi_c, void* stream) {
   if (int r = check_plan(p)) return r;
   if (!psi_c || !c) return fail(WVL_EINVAL, "wvl_compress: NULL pointer");
+  if (int r = check_aligned("wvl_compress", {c})) return r;
   if (int r = check_compressed(p, "wvl_compress")) return r;
   if (overlap(psi_c, cbatch_bytes(p), c, batch_bytes(p)))
     return fail(WVL_EINVAL, "wvl_compress: output overlaps input");
@@ -1617,6 +1637,7 @@ int wvl_plan_query(const wvl_plan* p, int32_t what, int64_t* value) {
 int wvl_overlap(wvl_plan* p, const void* c, double* S, void* ws, void* stream) {
   if (int r = check_plan(p)) return r;
   if (!c || !S || !ws) return fail(WVL_EINVAL, "wvl_overlap: NULL pointer");
+  if (int r = check_aligned("wvl_overlap", {c})) return r;
   if (!p->dense) return fail(WVL_EUNSUPPORTED, "wvl_overlap needs a dense uniform batch");
   if (int r = check_gpu(p)) return r;
   hipStream_t st = (hipStream_t)stream;
@@ -1662,6 +1683,7 @@ static int orthonormalize_into(wvl_plan* p, void* c, double* S, double* L, doubl
 static int check_orthonormalize(const wvl_plan* p, const void* c, const char* what) {
   if (int r = check_plan(p)) return r;
   if (!c) return fail(WVL_EINVAL, "%s: NULL pointer", what);
+  if (int r = check_aligned(what, {c})) return r;
   if (!p->dense) return fail(WVL_EUNSUPPORTED, "%s needs a dense uniform batch", what);
   if (p->norb > 256) return fail(WVL_EUNSUPPORTED, "%s supports up to 256 orbitals", what);
   return WVL_OK;

@@ -14,7 +14,7 @@
 // wavelet basis: per axis one value for scaling and one for wavelet
 // coefficients (OrbDev::kdiag), minus eps.  Every element kernel reads and
 // writes the plan's storage precision and computes in float64; dot products
-// are block partial sums (one per tile of 2048 points), summed per orbital in a
+// are block partial sums (one per tile of 8192 points), summed per orbital in a
 // fixed order by one workgroup, so results are deterministic.
 
 #include "wvl_kernels.h"
@@ -23,25 +23,31 @@ namespace wvl {
 
 struct CgScal { double alpha, beta, rz, pad; };
 
-// Tiles of the element kernels: kCgTile consecutive elements of one orbital,
-// in chunks of kCgPer per thread at a stride of kThreads (coalesced); the
-// loads of a chunk are issued before any is used, and a tile is long enough
-// to amortise the lookup of its orbital.  Each thread walks its elements with
-// the (x, y, z) position stepped incrementally, so the diagonal needs no
-// division per element.
-constexpr int kCgPer = 8;                      // elements per thread and chunk
+// Tiles of the element kernels: kCgTile consecutive elements of one orbital.
+// A thread moves groups of four consecutive elements (one 16-byte access per
+// plane, two in float64): orbital offsets and the plane length are multiples
+// of 8 elements (m1 m2 m3 = 8 n1 n2 n3) and batch arrays start on 16-byte
+// boundaries, so a group is aligned and never straddles two orbitals.  The
+// groups of a thread lie kThreads groups apart (coalesced), kCgG of them per
+// chunk with every load of the chunk issued before the first use.  Each
+// thread walks its groups with the (x, y, z) position stepped incrementally,
+// so the diagonal needs no division per element.
+constexpr int kCgG = 2;                        // groups per thread and chunk
+constexpr int kCgPer = 4 * kCgG;               // elements per thread and chunk
 constexpr int kCgChunks = 4;                   // chunks per tile
 constexpr int kCgTile = kThreads * kCgPer * kCgChunks;
+constexpr uint32_t kCgStep = 4 * kThreads;     // elements between a thread's groups
 
+// position of the first element of a thread's group
 struct CgPos {
   int x, y, z, dx, dy, dz, m1, m2;
-  __device__ CgPos(const OrbDev& od, uint32_t e0) : m1(od.m[0]), m2(od.m[1]) {
+  __device__ CgPos(const OrbDev& od, uint32_t e0, uint32_t step) : m1(od.m[0]), m2(od.m[1]) {
     const uint32_t row = e0 / (uint32_t)m1;
     x = (int)(e0 - row * (uint32_t)m1);
     y = (int)(row % (uint32_t)m2);
     z = (int)(row / (uint32_t)m2);
-    dx = kThreads % m1;
-    const int rows = kThreads / m1;
+    dx = (int)(step % (uint32_t)m1);
+    const int rows = (int)(step / (uint32_t)m1);
     dy = rows % m2;
     dz = rows / m2;
   }
@@ -51,11 +57,82 @@ struct CgPos {
     if (x >= m1) { x -= m1; ++cy; }
     y += cy;
     int cz = dz;
-    while (y >= m2) { y -= m2; ++cz; }
+    if (y >= m2) { y -= m2; ++cz; }
     z += cz;
   }
-  __device__ double diag(const OrbDev& od, double eps) const {
-    return od.kdiag[0][x & 1] + od.kdiag[1][y & 1] + od.kdiag[2][z & 1] - eps;
+};
+
+// 1 / diag per parity class (x, y, z mod 2) of one orbital: diag is the
+// kinetic diagonal of the wavelet basis, one value per axis for scaling and
+// one for wavelet coefficients, minus eps.
+struct CgInv {
+  double v[8];   // index (z & 1) << 2 | (y & 1) << 1 | (x & 1)
+  __device__ CgInv(const OrbDev& od, double eps) {
+    #pragma unroll
+    for (int k = 0; k < 8; ++k)
+      v[k] = 1.0 / (od.kdiag[0][k & 1] + od.kdiag[1][(k >> 1) & 1] + od.kdiag[2][k >> 2] - eps);
+  }
+  // the four elements of the group at p: x is even (the group starts at a
+  // multiple of 4 and m1 is even), so element j has x parity j & 1; elements
+  // 2 and 3 move to the next row when x = m1 - 2 (m2 even: the parity of y
+  // + 1 is right also where it wraps to 0, and z advances with it)
+  __device__ void group(const CgPos& p, double (&w)[4]) const {
+    const int wrap = p.x + 2 >= p.m1 ? 1 : 0;
+    const int y1 = p.y + wrap;
+    const int z1 = p.z + (y1 == p.m2 ? 1 : 0);
+    pair(p.y & 1, p.z & 1, w[0], w[1]);
+    pair(y1 & 1, z1 & 1, w[2], w[3]);
+  }
+  __device__ void pair(int py, int pz, double& a0, double& a1) const {
+    a0 = pz ? (py ? v[6] : v[4]) : (py ? v[2] : v[0]);
+    a1 = pz ? (py ? v[7] : v[5]) : (py ? v[3] : v[1]);
+  }
+};
+
+// loads and stores of one group in the plan's storage precision, as float64
+template <int P> struct G4;
+template <> struct G4<F64> {
+  __device__ static void ld(const void* p, int64_t i, int64_t, double (&v)[4]) {
+    const double2* q = reinterpret_cast<const double2*>((const double*)p + i);
+    const double2 a = q[0], b = q[1];
+    v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
+  }
+  __device__ static void st(void* p, int64_t i, int64_t, const double (&v)[4]) {
+    double2* q = reinterpret_cast<double2*>((double*)p + i);
+    q[0] = make_double2(v[0], v[1]);
+    q[1] = make_double2(v[2], v[3]);
+  }
+};
+template <> struct G4<F32> {
+  __device__ static void ld(const void* p, int64_t i, int64_t, double (&v)[4]) {
+    const float4 a = *reinterpret_cast<const float4*>((const float*)p + i);
+    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+  }
+  __device__ static void st(void* p, int64_t i, int64_t, const double (&v)[4]) {
+    *reinterpret_cast<float4*>((float*)p + i) =
+        make_float4((float)v[0], (float)v[1], (float)v[2], (float)v[3]);
+  }
+};
+template <> struct G4<F32C> {
+  __device__ static void ld(const void* p, int64_t i, int64_t plane, double (&v)[4]) {
+    const float* f = (const float*)p;
+    const float4 h = *reinterpret_cast<const float4*>(f + i);
+    const float4 l = *reinterpret_cast<const float4*>(f + plane + i);
+    v[0] = (double)h.x + (double)l.x;
+    v[1] = (double)h.y + (double)l.y;
+    v[2] = (double)h.z + (double)l.z;
+    v[3] = (double)h.w + (double)l.w;
+  }
+  __device__ static void st(void* p, int64_t i, int64_t plane, const double (&v)[4]) {
+    float h[4], l[4];
+    #pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      h[k] = (float)v[k];
+      l[k] = (float)(v[k] - (double)h[k]);
+    }
+    float* f = (float*)p;
+    *reinterpret_cast<float4*>(f + i) = make_float4(h[0], h[1], h[2], h[3]);
+    *reinterpret_cast<float4*>(f + plane + i) = make_float4(l[0], l[1], l[2], l[3]);
   }
 };
 
@@ -64,28 +141,34 @@ __global__ __launch_bounds__(kThreads) void k_cg_init(PassGeom g, const void* gi
                                                       void* p, const double* __restrict__ eps,
                                                       int64_t plane, double* prz, double* ppp,
                                                       double* prr) {
-  using T = Prec<P>;
+  using L = G4<P>;
   int b, t;
   find_tile(g.prefix, g.norb, blockIdx.x, b, t);
   const OrbDev od = g.orbs[b];
   const uint32_t M = (uint32_t)od.m[0] * od.m[1] * od.m[2];
-  const uint32_t e0 = (uint32_t)t * kCgTile + threadIdx.x;
-  const double ep = eps[b];
+  const uint32_t e0 = (uint32_t)t * kCgTile + 4 * threadIdx.x;
+  const CgInv inv(od, eps[b]);
   double rz = 0.0, pp = 0.0, rr = 0.0;
-  CgPos pos(od, e0);
+  CgPos pos(od, e0, kCgStep);
+  const double zero[4] = {0.0, 0.0, 0.0, 0.0};
   #pragma unroll 1
-  for (int k = 0; k < kCgPer * kCgChunks; ++k) {
-    const uint32_t e = e0 + (uint32_t)k * kThreads;
+  for (int k = 0; k < kCgG * kCgChunks; ++k) {
+    const uint32_t e = e0 + (uint32_t)k * kCgStep;
     if (e < M) {
       const int64_t i = od.off + e;
-      const double rv = T::d(T::ldc(gin, i, plane));
-      const double z = rv / pos.diag(od, ep);
-      T::st(r, i, plane, T::from_d(rv));
-      T::st(p, i, plane, T::from_d(z));
-      T::st(x, i, plane, T::from_d(0.0));
-      rz += rv * z;
-      pp += z * z;
-      rr += rv * rv;
+      double rv[4], zv[4], w[4];
+      L::ld(gin, i, plane, rv);
+      inv.group(pos, w);
+      #pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        zv[j] = rv[j] * w[j];
+        rz += rv[j] * zv[j];
+        pp += zv[j] * zv[j];
+        rr += rv[j] * rv[j];
+      }
+      L::st(r, i, plane, rv);
+      L::st(p, i, plane, zv);
+      L::st(x, i, plane, zero);
     }
     pos.next();
   }
@@ -140,48 +223,53 @@ __global__ __launch_bounds__(kThreads) void k_cg_update1(PassGeom g, void* x, vo
                                                          const void* q, const double* __restrict__ eps,
                                                          int shift, const CgScal* __restrict__ sc,
                                                          int64_t plane, double* prz, double* prr) {
-  using T = Prec<P>;
+  using L = G4<P>;
   int b, t;
   find_tile(g.prefix, g.norb, blockIdx.x, b, t);
   const OrbDev od = g.orbs[b];
   const uint32_t M = (uint32_t)od.m[0] * od.m[1] * od.m[2];
-  const uint32_t e0 = (uint32_t)t * kCgTile + threadIdx.x;
+  const uint32_t e0 = (uint32_t)t * kCgTile + 4 * threadIdx.x;
   const double a = sc[b].alpha, ep = eps[b];
   const double sh = shift ? ep : 0.0;
+  const CgInv inv(od, ep);
   double rz = 0.0, rr = 0.0;
-  CgPos pos(od, e0);
+  CgPos pos(od, e0, kCgStep);
   #pragma unroll 1
   for (int ch = 0; ch < kCgChunks; ++ch) {
-  const uint32_t c0 = e0 + (uint32_t)(ch * kCgPer) * kThreads;
-  // every load of the chunk is issued before the first use
-  double pv[kCgPer], qv[kCgPer], xv[kCgPer], rv[kCgPer];
-  #pragma unroll
-  for (int k = 0; k < kCgPer; ++k) {
-    const uint32_t e = c0 + (uint32_t)k * kThreads;
-    pv[k] = qv[k] = xv[k] = rv[k] = 0.0;
-    if (e < M) {
-      const int64_t i = od.off + e;
-      pv[k] = T::d(T::ldc(p, i, plane));
-      qv[k] = T::d(T::ldc(q, i, plane));
-      xv[k] = T::d(T::ldc(x, i, plane));
-      rv[k] = T::d(T::ldc(r, i, plane));
+    const uint32_t c0 = e0 + (uint32_t)(ch * kCgG) * kCgStep;
+    // every load of the chunk is issued before the first use
+    double pv[kCgG][4], qv[kCgG][4], xv[kCgG][4], rv[kCgG][4];
+    #pragma unroll
+    for (int k = 0; k < kCgG; ++k) {
+      const uint32_t e = c0 + (uint32_t)k * kCgStep;
+      if (e < M) {
+        const int64_t i = od.off + e;
+        L::ld(p, i, plane, pv[k]);
+        L::ld(q, i, plane, qv[k]);
+        L::ld(x, i, plane, xv[k]);
+        L::ld(r, i, plane, rv[k]);
+      }
     }
-  }
-  #pragma unroll
-  for (int k = 0; k < kCgPer; ++k) {
-    const uint32_t e = c0 + (uint32_t)k * kThreads;
-    if (e < M) {
-      const int64_t i = od.off + e;
-      const double qs = qv[k] - sh * pv[k];
-      const double xn = xv[k] + a * pv[k];
-      const double rn = rv[k] - a * qs;
-      T::st(x, i, plane, T::from_d(xn));
-      T::st(r, i, plane, T::from_d(rn));
-      rz += rn * (rn / pos.diag(od, ep));
-      rr += rn * rn;
+    #pragma unroll
+    for (int k = 0; k < kCgG; ++k) {
+      const uint32_t e = c0 + (uint32_t)k * kCgStep;
+      if (e < M) {
+        const int64_t i = od.off + e;
+        double w[4], xn[4], rn[4];
+        inv.group(pos, w);
+        #pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const double qs = qv[k][j] - sh * pv[k][j];
+          xn[j] = xv[k][j] + a * pv[k][j];
+          rn[j] = rv[k][j] - a * qs;
+          rz += rn[j] * (rn[j] * w[j]);
+          rr += rn[j] * rn[j];
+        }
+        L::st(x, i, plane, xn);
+        L::st(r, i, plane, rn);
+      }
+      pos.next();
     }
-    pos.next();
-  }
   }
   block_sum_store(rz, prz + blockIdx.x);
   block_sum_store(rr, prr + blockIdx.x);
@@ -204,40 +292,45 @@ __global__ __launch_bounds__(kThreads) void k_cg_update2(PassGeom g, const void*
                                                          const double* __restrict__ eps,
                                                          const CgScal* __restrict__ sc,
                                                          int64_t plane, double* ppp) {
-  using T = Prec<P>;
+  using L = G4<P>;
   int b, t;
   find_tile(g.prefix, g.norb, blockIdx.x, b, t);
   const OrbDev od = g.orbs[b];
   const uint32_t M = (uint32_t)od.m[0] * od.m[1] * od.m[2];
-  const uint32_t e0 = (uint32_t)t * kCgTile + threadIdx.x;
-  const double beta = sc[b].beta, ep = eps[b];
+  const uint32_t e0 = (uint32_t)t * kCgTile + 4 * threadIdx.x;
+  const double beta = sc[b].beta;
+  const CgInv inv(od, eps[b]);
   double pp = 0.0;
-  CgPos pos(od, e0);
+  CgPos pos(od, e0, kCgStep);
   #pragma unroll 1
   for (int ch = 0; ch < kCgChunks; ++ch) {
-  const uint32_t c0 = e0 + (uint32_t)(ch * kCgPer) * kThreads;
-  double rv[kCgPer], pv[kCgPer];
-  #pragma unroll
-  for (int k = 0; k < kCgPer; ++k) {
-    const uint32_t e = c0 + (uint32_t)k * kThreads;
-    rv[k] = pv[k] = 0.0;
-    if (e < M) {
-      const int64_t i = od.off + e;
-      rv[k] = T::d(T::ldc(r, i, plane));
-      pv[k] = T::d(T::ldc(p, i, plane));
+    const uint32_t c0 = e0 + (uint32_t)(ch * kCgG) * kCgStep;
+    double rv[kCgG][4], pv[kCgG][4];
+    #pragma unroll
+    for (int k = 0; k < kCgG; ++k) {
+      const uint32_t e = c0 + (uint32_t)k * kCgStep;
+      if (e < M) {
+        const int64_t i = od.off + e;
+        L::ld(r, i, plane, rv[k]);
+        L::ld(p, i, plane, pv[k]);
+      }
     }
-  }
-  #pragma unroll
-  for (int k = 0; k < kCgPer; ++k) {
-    const uint32_t e = c0 + (uint32_t)k * kThreads;
-    if (e < M) {
-      const int64_t i = od.off + e;
-      const double pn = rv[k] / pos.diag(od, ep) + beta * pv[k];
-      T::st(p, i, plane, T::from_d(pn));
-      pp += pn * pn;
+    #pragma unroll
+    for (int k = 0; k < kCgG; ++k) {
+      const uint32_t e = c0 + (uint32_t)k * kCgStep;
+      if (e < M) {
+        const int64_t i = od.off + e;
+        double w[4], pn[4];
+        inv.group(pos, w);
+        #pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          pn[j] = rv[k][j] * w[j] + beta * pv[k][j];
+          pp += pn[j] * pn[j];
+        }
+        L::st(p, i, plane, pn);
+      }
+      pos.next();
     }
-    pos.next();
-  }
   }
   block_sum_store(pp, ppp + blockIdx.x);
 }

@@ -147,7 +147,7 @@ def test_partial_overlap_is_rejected(dry, prec):
     f = lib.raw
     a, V, ws = 0x100000, ctypes.c_void_p(0x200000), ctypes.c_void_p(0x300000)
     A = ctypes.c_void_p(a)
-    inside = ctypes.c_void_p(a + 8)
+    inside = ctypes.c_void_p(a + 16)
     nbytes = 2 * 512 * (4 if prec == 1 else 8)
     after = ctypes.c_void_p(a + nbytes)      # first byte past the array: disjoint
     hpsi = f("wvl_local_hpsi")
@@ -166,6 +166,39 @@ def test_partial_overlap_is_rejected(dry, prec):
     assert f("wvl_kinetic")(p, A, k0_inside_out, out, ws, None) == lib.WVL_EINVAL
     assert f("wvl_kinetic")(p, A, out, out, ws, None) == lib.WVL_ENODEV
     assert f("wvl_kinetic")(p, A, inside, out, ws, None) == lib.WVL_EINVAL
+    lib.wvl_plan_destroy(p)
+
+
+def test_misaligned_batch_arrays_are_rejected(dry):
+    """Batch arrays must start on a 16-byte boundary (every entry point that
+    takes one checks it before any GPU work)."""
+    rc, p = _plan(dry, [(4, 4, 4)] * 2)
+    assert rc == lib.WVL_OK
+    f = lib.raw
+    A, V, ws = ctypes.c_void_p(0x100000), ctypes.c_void_p(0x200000), ctypes.c_void_p(0x300000)
+    out = ctypes.c_void_p(0x400000)
+    odd = ctypes.c_void_p(0x500008)
+    S = ctypes.c_void_p(0x600000)
+    eps = (ctypes.c_double * 2)(-0.5, -0.2)
+    calls = {
+        "wvl_synthesis": lambda x, y: f("wvl_synthesis")(p, x, y, ws, None),
+        "wvl_analysis": lambda x, y: f("wvl_analysis")(p, x, y, ws, None),
+        "wvl_magic_filter": lambda x, y: f("wvl_magic_filter")(p, x, y, 0, ws, None),
+        "wvl_kinetic": lambda x, y: f("wvl_kinetic")(p, x, None, y, ws, None),
+        "wvl_local_hpsi": lambda x, y: f("wvl_local_hpsi")(p, x, V, 1.0, 1.0, y, None, None,
+                                                           None, None, ws, None),
+        "wvl_energy_gradient": lambda x, y: f("wvl_energy_gradient")(p, x, V, 1.0, 1.0, y, ws,
+                                                                     None),
+        "wvl_precondition": lambda x, y: f("wvl_precondition")(p, x, eps, 2, 0, y, None, ws, None),
+    }
+    for name, call in calls.items():
+        for x, y in ((odd, out), (A, odd)):
+            assert call(x, y) == lib.WVL_EINVAL, name
+            assert "16-byte aligned" in lib.wvl_last_error(), name
+        assert call(A, out) == lib.WVL_ENODEV, name
+    assert f("wvl_local_density")(p, odd, S, 0, ws, None) == lib.WVL_EINVAL
+    assert f("wvl_overlap")(p, odd, S, ws, None) == lib.WVL_EINVAL
+    assert f("wvl_orthonormalize")(p, odd, S, S, ws, None) == lib.WVL_EINVAL
     lib.wvl_plan_destroy(p)
 
 
