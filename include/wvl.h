@@ -269,7 +269,7 @@ int wvl_orthonormalize(wvl_plan *plan, void *c, double *S, double *L, void *ws, 
 /* wvl_orthonormalize for callers that cannot allocate device memory (code
  * under hipGraph capture, tight serving loops, harnesses that forbid
  * hipMalloc): the same operation and the same kernels, but the scratch memory
- * (overlap slice partials, L, L^{-1}, product scratch) is a static device
+ * (overlap slice partials, L, L^{-1}) is a static device
  * array of the library instead of a caller workspace, so no `ws` argument.
  * The array holds 80 MiB on every GPU the library runs on, from the first
  * wvl_create() on that device until the process ends; every batch of up to

@@ -142,7 +142,7 @@ struct wvl_plan {
   int32_t *d_map_c = nullptr, *d_map_f = nullptr, *d_list_c = nullptr, *d_list_f = nullptr;
   // workspace layout (byte offsets)
   size_t ws = 0, o_A = 0, o_B = 0, o_S = 0, o_D = 0, o_cg = 0, o_ez = 0, o_ey = 0, o_ex = 0, o_pp = 0, o_rv = 0,
-         o_rho = 0, o_eorb = 0, o_syrk = 0, o_L = 0, o_Li = 0, o_T = 0, o_rhop = 0, o_epl = 0,
+         o_rho = 0, o_eorb = 0, o_syrk = 0, o_L = 0, o_Li = 0, o_rhop = 0, o_epl = 0,
          o_kpl = 0, o_queue = 0, o_ozv = 0, o_oze = 0, o_kpl2 = 0;
   // graph cache
   hipStream_t gstream = nullptr;
@@ -546,7 +546,6 @@ int wvl_plan_create(wvl_ctx* ctx, const wvl_orbital* orbs, int32_t norb, int32_t
     p->o_syrk = off; off += align256(sizeof(double) * (size_t)syrk_partials(norb, p->M));
     p->o_L = off; off += align256(sizeof(double) * (size_t)norb * norb);
     p->o_Li = off; off += align256(sizeof(double) * (size_t)norb * norb);
-    p->o_T = off; off += align256(sizeof(double) * (size_t)norb * norb);
   }
   if (p->xy_ok || p->oz_pc) {   // the plane path may be chosen later by the tuner
     if (p->shared) {
@@ -1653,7 +1652,7 @@ int wvl_overlap(wvl_plan* p, const void* c, double* S, void* ws, void* stream) {
 // Overlap, Cholesky and X <- L^{-1} X with the scratch arrays given (SYRK
 // slice partials, L, L^{-1}, a product scratch).
 static int orthonormalize_into(wvl_plan* p, void* c, double* S, double* L, double* syrk, double* Lw,
-                               double* Li, double* T, hipStream_t st) {
+                               double* Li, hipStream_t st) {
   const size_t nn = sizeof(double) * (size_t)p->norb * p->norb;
   hipError_t e;
   {
@@ -1664,8 +1663,7 @@ static int orthonormalize_into(wvl_plan* p, void* c, double* S, double* L, doubl
   if (S) WVL_HIP(hipMemcpyAsync(S, Lw, nn, hipMemcpyDeviceToDevice, st));
   {
     Mark mk(p, st, ST_CHOL);
-    e = launch_cholesky_inv(Lw, Li, T, p->norb, p->d_info, st);
-    if (e == hipSuccess) e = launch_linv_offdiag(Lw, Li, T, p->norb, st);
+    e = launch_cholesky_inv(Lw, Li, p->norb, p->d_info, st);
   }
   if (e != hipSuccess) return hipfail(e, "cholesky");
   if (L) {
@@ -1730,17 +1728,17 @@ int wvl_orthonormalize(wvl_plan* p, void* c, double* S, double* L, void* ws, voi
   if (!ws) return fail(WVL_EINVAL, "wvl_orthonormalize: NULL workspace");
   if (int r = check_gpu(p)) return r;
   return orthonormalize_into(p, c, S, L, (double*)wsp(ws, p->o_syrk), (double*)wsp(ws, p->o_L),
-                             (double*)wsp(ws, p->o_Li), (double*)wsp(ws, p->o_T),
+                             (double*)wsp(ws, p->o_Li),
                              (hipStream_t)stream);
 }
 
 int wvl_orthonormalize_noalloc(wvl_plan* p, void* c, double* S, double* L, void* stream) {
   if (int r = check_orthonormalize(p, c, "wvl_orthonormalize_noalloc")) return r;
-  // scratch layout: SYRK slice partials, then L, L^{-1} and the product
-  // scratch (n x n each), every part 256-byte aligned
+  // scratch layout: SYRK slice partials, then L and L^{-1} (n x n each),
+  // every part 256-byte aligned
   const size_t nn = align256(sizeof(double) * (size_t)p->norb * p->norb);
   const size_t syrk = align256(sizeof(double) * (size_t)syrk_partials(p->norb, p->M));
-  const size_t need = syrk + 3 * nn;
+  const size_t need = syrk + 2 * nn;
   if (need > kScratchBytes)
     return fail(WVL_EUNSUPPORTED,
                 "wvl_orthonormalize_noalloc: needs %zu bytes of scratch, the library holds %zu",
@@ -1750,7 +1748,7 @@ int wvl_orthonormalize_noalloc(wvl_plan* p, void* c, double* S, double* L, void*
   if (!base) return fail(WVL_EHIP, "wvl_orthonormalize_noalloc: scratch not set up on device %d",
                          p->ctx->device);
   return orthonormalize_into(p, c, S, L, (double*)base, (double*)(base + syrk),
-                             (double*)(base + syrk + nn), (double*)(base + syrk + 2 * nn),
+                             (double*)(base + syrk + nn),
                              (hipStream_t)stream);
 }
 

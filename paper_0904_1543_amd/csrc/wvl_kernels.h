@@ -245,12 +245,10 @@ hipError_t launch_rho_reduce(const double* part, int ngroups, int64_t M, const d
 int64_t syrk_partials(int norb, int64_t len);
 hipError_t launch_overlap_p(int prec, const void* X, int64_t plane, int norb, int64_t len,
                             double* S, double* work, hipStream_t st);
-// Blocked Cholesky: S (n x n, overwritten with L, upper part not touched
-// except diagonal blocks), Linv diagonal blocks, T scratch (n x n).
-hipError_t launch_cholesky_inv(double* S, double* Linv, double* T, int n, int* info,
-                               hipStream_t st);
-// Off-diagonal blocks of Linv from L and the diagonal inverse blocks.
-hipError_t launch_linv_offdiag(const double* L, double* Linv, double* T, int n, hipStream_t st);
+// Blocked Cholesky (n <= 256, one launch): S (n x n) overwritten with L
+// (upper part not touched except the diagonal blocks), Linv = L^{-1} (n x n,
+// zero above the diagonal); info[0] = first non-positive pivot row + 1.
+hipError_t launch_cholesky_inv(double* S, double* Linv, int n, int* info, hipStream_t st);
 // L output: the lower triangle of the factorised S.
 hipError_t launch_chol_factor(const double* S, const double* Linv, int norb, double* L,
                               hipStream_t st);

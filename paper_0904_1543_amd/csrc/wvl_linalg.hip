@@ -14,8 +14,9 @@
 //    of the lower triangle; for more orbitals one wave owns a 64x64 block over
 //    a slice, reading its rows as whole 128-byte lines, with the blocks of one
 //    slice placed on one XCD.  Slice partials are summed in a fixed order;
-//  * blocked Cholesky and L^{-1} with 64 x 64 diagonal blocks factorised in
-//    LDS and small float64 products for the panels and the trailing updates;
+//  * blocked Cholesky and L^{-1} in one single-workgroup launch: 32 x 32
+//    diagonal blocks factorised in registers, panels, trailing updates and
+//    the blocks of L^{-1} on the float64 matrix cores;
 //  * X <- L^{-1} X on the matrix cores, skipping the zero blocks of L^{-1}.
 
 #include "wvl_kernels.h"
@@ -354,125 +355,257 @@ hipError_t launch_overlap_p(int prec, const void* X, int64_t plane, int norb, in
 }
 
 // ---------------------------------------------------------------------------
-// Blocked Cholesky S = L L^T and Linv = L^{-1} (n <= 256, blocks of 64).
-// For block column J: the diagonal block is factorised and inverted in LDS by
-// one workgroup; the panel below is L_IJ = S_IJ inv(L_JJ)^T; the trailing
-// lower triangle is updated S_IK -= L_IJ L_KJ^T.  Then block row I of Linv is
-// Linv_I,0:I = -inv(L_II) (L_I,0:I Linv_0:I,0:I).  All small products use one
-// strided float64 GEMM kernel; results are deterministic.
+// Cholesky S = L L^T and Linv = L^{-1} (n <= 256) in one launch of one
+// workgroup (8 waves); S, L and Linv stay in the L2 cache between the steps.
+// Right-looking, by block columns J of 32, with the inverse built alongside
+// as the solution Y of L Y = I by the same elimination (Linv holds the
+// updated right-hand side R of the block rows not yet reached):
+//  * the panel (rows r0.. of the block column) is staged in LDS;
+//  * wave 0 factorises the diagonal block with its rows in registers (lane r
+//    holds row r; each column of L is broadcast through LDS) and inverts it
+//    by forward elimination alongside (lane c holds column c of inv(L_JJ));
+//  * the panel below becomes L_IJ = S_IJ inv(L_JJ)^T;
+//  * block row J of Linv: Y_J,K = inv(L_JJ) R_J,K (K < J), Y_J,J = inv(L_JJ);
+//  * the rows below are updated: S_IK -= L_IJ L_KJ^T (trailing lower
+//    triangle) and R_I,0:J+1 -= L_IJ Y_J,0:J+1.
+// All products run on the float64 matrix cores from LDS operands; the
+// read-modify-writes of S and R are batched four tiles at a time.  A
+// non-positive pivot sets info[0] to its row + 1 (the first one only) and is
+// replaced by 1.
 // ---------------------------------------------------------------------------
-constexpr int kCb = 64;
+constexpr int kCb = 32;                  // diagonal block
+constexpr int kChPitch = 36;             // doubles per staged panel row
+constexpr int kChRows = 256;             // panel rows staged (n <= 256)
+constexpr int kChYPitch = kChRows + 4;   // doubles per staged row of Y_J
+constexpr int kChThreads = 512;
 
-// diagonal block at (r0, r0) of size b <= 64: L_JJ in place (upper part
-// zeroed), inv(L_JJ) to D (leading dimension ldd).  info[0] = first bad pivot + 1.
-__global__ __launch_bounds__(256) void k_potrf_block(double* A, int lda, int r0, int b, double* D,
-                                                     int ldd, int* info) {
-  // LDS: a (the block, factorised in place) and m (its inverse), rows padded
-  // to an odd pitch so that a column read by 64 lanes hits distinct banks.
-  // Thread t owns row r = t mod 64 and the 16 columns of quarter t / 64.
-  extern __shared__ double lds_potrf[];
-  constexpr int P = kCb + 1;
-  double* a = lds_potrf;
-  double* m = lds_potrf + kCb * P;
-  const int t = threadIdx.x;
-  const int r = t & 63, cq = t >> 6;
-  // every load is issued (outside the block: a valid element, discarded)
-  // before the first is used, so their latencies overlap
-  double v[16];
-  #pragma unroll
-  for (int kk = 0; kk < 16; ++kk) {
-    const int k = cq * 16 + kk;
-    const bool in = r < b && k < b;
-    v[kk] = A[in ? (int64_t)(r0 + r) * lda + r0 + k : (int64_t)r0 * lda + r0];
-  }
-  #pragma unroll
-  for (int kk = 0; kk < 16; ++kk) {
-    const int k = cq * 16 + kk;
-    const bool in = r < b && k < b;
-    a[r * P + k] = in ? v[kk] : (r == k ? 1.0 : 0.0);
-    m[r * P + k] = (r == k) ? 1.0 : 0.0;
-  }
+__device__ __forceinline__ double rd_lane(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// row and column tile of pair p of the lower triangle of nt x nt tiles
+__device__ __forceinline__ void tri_pair(int p, int& it, int& kt) {
+  it = 0;
+  while ((it + 1) * (it + 2) / 2 <= p) ++it;
+  kt = p - it * (it + 1) / 2;
+}
+
+__global__ __launch_bounds__(kChThreads) void k_chol_inv(double* __restrict__ A,
+                                                         double* __restrict__ Li, int n,
+                                                         int* __restrict__ info) {
+  extern __shared__ double lds_chol[];
+  double* pan = lds_chol;                          // kChRows x kChPitch
+  double* dinv = pan + kChRows * kChPitch;         // kCb x kChPitch: inv(L_JJ)
+  double* col = dinv + kCb * kChPitch;             // kCb: one column of L_JJ
+  double* yb = col + kCb;                          // kCb x kChYPitch: Y_J,0:J+1
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  constexpr int NW = kChThreads / 64;
+  const int li = lane & 15, q = lane >> 4;
+  const int nb = (n + kCb - 1) / kCb;
+  // R = 0 off the diagonal blocks (the diagonal blocks are written as found)
+  for (int idx = tid; idx < n * n; idx += kChThreads) Li[idx] = 0.0;
   __syncthreads();
-  // right-looking unblocked Cholesky
-  for (int j = 0; j < b; ++j) {
-    double d = a[j * P + j];
-    if (!(d > 0.0)) {
-      if (t == 0 && info[0] == 0) info[0] = r0 + j + 1;
-      d = 1.0;
+  for (int J = 0; J < nb; ++J) {
+    const int r0 = J * kCb, b = min(kCb, n - r0), nr = n - r0;
+    // panel rows 0..kChRows-1 (relative to r0): S values, the diagonal block
+    // padded with the identity, zero below the matrix
+    #pragma unroll 4
+    for (int idx = tid; idx < kChRows * kCb; idx += kChThreads) {
+      const int i = idx / kCb, c = idx - i * kCb;
+      double v = (i == c) ? 1.0 : 0.0;
+      if (i < nr && c < b) v = A[(int64_t)(r0 + i) * n + r0 + c];
+      pan[i * kChPitch + c] = v;
     }
-    const double l = sqrt(d);
-    __syncthreads();   // every thread has read the pivot
-    if (cq == 0 && r > j && r < b) a[r * P + j] /= l;
-    if (t == 0) a[j * P + j] = l;
     __syncthreads();
-    if (r > j && r < b) {
-      const double lr = a[r * P + j];
+    if (wave == 0) {
+      // lane r: row r of the block (a) and column r of its inverse (x, by
+      // forward elimination on the identity, one column of L at a time);
+      // r is opaque so that nothing depending on it leaves the J loop
+      int r = lane & (kCb - 1);
+      asm volatile("" : "+v"(r));
+      double a[kCb], x[kCb];
       #pragma unroll
-      for (int kk = 0; kk < 16; ++kk) {
-        const int k = cq * 16 + kk;
-        if (k > j && k <= r) a[r * P + k] -= lr * a[k * P + j];
+      for (int c = 0; c < kCb; ++c) {
+        a[c] = pan[r * kChPitch + c];
+        x[c] = (c == r) ? 1.0 : 0.0;
       }
-    }
-    __syncthreads();
-  }
-  // inverse by forward elimination on [L | I]
-  for (int j = 0; j < b; ++j) {
-    const double inv = 1.0 / a[j * P + j];
-    if (t <= j) m[j * P + t] *= inv;
-    __syncthreads();
-    if (r > j && r < b) {
-      const double lr = a[r * P + j];
       #pragma unroll
-      for (int kk = 0; kk < 16; ++kk) {
-        const int k = cq * 16 + kk;
-        if (k <= j) m[r * P + k] -= lr * m[j * P + k];
+      for (int j = 0; j < kCb; ++j) {
+        double d = rd_lane(a[j], j);
+        if (!(d > 0.0)) {
+          if (lane == 0 && j < b && info[0] == 0) info[0] = r0 + j + 1;
+          d = 1.0;
+        }
+        const double l = sqrt(d), il = 1.0 / l;
+        // rows above j (r < j) hold the unused upper part: updated too, never read
+        a[j] = (r == j) ? l : a[j] * il;
+        // column j of L to every lane (LDS broadcast reads)
+        if (lane < kCb) col[r] = a[j];
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        x[j] *= il;
+        double lk[kCb];
+        #pragma unroll
+        for (int k = j + 1; k < kCb; ++k) lk[k] = col[k];
+        #pragma unroll
+        for (int k = j + 1; k < kCb; ++k) {
+          a[k] = __builtin_fma(-a[j], lk[k], a[k]);
+          x[k] = __builtin_fma(-lk[k], x[j], x[k]);
+        }
+        // applied now: the updates are not deferred to their use (which
+        // would hold every column in registers)
+        #pragma unroll
+        for (int k = j + 1; k < kCb; ++k) asm volatile("" : "+v"(a[k]), "+v"(x[k]));
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+      }
+      if (lane < kCb) {
+        #pragma unroll
+        for (int c = 0; c < kCb; ++c) {
+          pan[r * kChPitch + c] = c <= r ? a[c] : 0.0;
+          dinv[c * kChPitch + r] = x[c];
+        }
       }
     }
     __syncthreads();
-  }
-  if (r < b) {
-    for (int kk = 0; kk < 16; ++kk) {
-      const int k = cq * 16 + kk;
-      if (k < b) {
-        A[(int64_t)(r0 + r) * lda + r0 + k] = (k <= r) ? a[r * P + k] : 0.0;
-        D[(int64_t)r * ldd + k] = (k <= r) ? m[r * P + k] : 0.0;
+    // the diagonal blocks of L and Linv to memory (L's upper part zero);
+    // Y_J,J = inv(L_JJ) staged as columns r0.. of yb
+    for (int idx = tid; idx < kCb * kCb; idx += kChThreads) {
+      const int i = idx / kCb, c = idx - i * kCb;
+      yb[i * kChYPitch + r0 + c] = dinv[i * kChPitch + c];
+      if (i < b && c < b) {
+        A[(int64_t)(r0 + i) * n + r0 + c] = pan[i * kChPitch + c];
+        Li[(int64_t)(r0 + i) * n + r0 + c] = dinv[i * kChPitch + c];
       }
     }
+    // block row J of Linv: Y_J,K = inv(L_JJ) R_J,K for the column tiles left
+    // of the diagonal block (both row tiles of a column tile in one wave: the
+    // tile is read whole before it is overwritten)
+    for (int kt = wave; kt < (r0 >> 4); kt += NW) {
+      double bv[kCb / 4];
+      #pragma unroll
+      for (int s = 0; s < kCb / 4; ++s) {
+        const int m = 4 * s + q;
+        bv[s] = m < b ? Li[(int64_t)(r0 + m) * n + 16 * kt + li] : 0.0;
+      }
+      #pragma unroll
+      for (int it = 0; it < 2; ++it) {
+        d4 y = d4{0.0, 0.0, 0.0, 0.0};
+        #pragma unroll
+        for (int s = 0; s < kCb / 4; ++s)
+          y = __builtin_amdgcn_mfma_f64_16x16x4f64(dinv[(16 * it + li) * kChPitch + 4 * s + q], bv[s],
+                                                   y, 0, 0, 0);
+        #pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = 16 * it + q + 4 * v;
+          yb[row * kChYPitch + 16 * kt + li] = y[v];
+          if (row < b) Li[(int64_t)(r0 + row) * n + 16 * kt + li] = y[v];
+        }
+      }
+    }
+    const int rem = nr - b;
+    if (rem <= 0) break;
+    const int nt = (rem + 15) >> 4;               // 16-row tiles below the diagonal block
+    // panel: L_IJ = S_IJ inv(L_JJ)^T, tile (it, ct) -> rows b + 16 it, columns 16 ct
+    d4 acc[4];
+    #pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      acc[u] = d4{0.0, 0.0, 0.0, 0.0};
+      const int tt = wave + u * NW;
+      if (tt >= 2 * nt) continue;
+      const int it = tt >> 1, ct = tt & 1;
+      #pragma unroll
+      for (int s = 0; s < kCb / 4; ++s) {
+        const double av = pan[(b + 16 * it + li) * kChPitch + 4 * s + q];
+        const double bw = dinv[(16 * ct + li) * kChPitch + 4 * s + q];
+        acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bw, acc[u], 0, 0, 0);
+      }
+    }
+    __syncthreads();
+    // element (i, j) of a tile: lane j + 16 (i mod 4), register i / 4
+    #pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int tt = wave + u * NW;
+      if (tt >= 2 * nt) continue;
+      const int it = tt >> 1, ct = tt & 1;
+      #pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = b + 16 * it + q + 4 * v, c = 16 * ct + li;
+        pan[row * kChPitch + c] = acc[u][v];
+        if (row < nr) A[(int64_t)(r0 + row) * n + r0 + c] = acc[u][v];
+      }
+    }
+    __syncthreads();
+    // rows below: tiles of the trailing lower triangle of S (pairs it >= kt)
+    // and of R_I,0:J+1 (nt x ncy), four per wave at a time, each tile's
+    // target read before the products
+    const int npair = nt * (nt + 1) / 2, ncy = (r0 + kCb) >> 4;
+    const int ntot = npair + nt * ncy;
+    for (int t0 = wave; t0 < ntot; t0 += 4 * NW) {
+      double cv[4][4];
+      double* dst[4];
+      int ti[4], tk[4];
+      bool ys[4], ok[4];
+      #pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int tt = t0 + u * NW;
+        ok[u] = tt < ntot;
+        ys[u] = tt >= npair;
+        if (ys[u]) {
+          ti[u] = (tt - npair) / ncy;
+          tk[u] = (tt - npair) - ti[u] * ncy;
+          dst[u] = Li + (int64_t)(r0 + b + 16 * ti[u]) * n + 16 * tk[u];
+        } else {
+          tri_pair(tt, ti[u], tk[u]);
+          dst[u] = A + (int64_t)(r0 + b + 16 * ti[u]) * n + r0 + b + 16 * tk[u];
+        }
+        const int cmax = ys[u] ? n : nr - b - 16 * tk[u];
+        #pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = b + 16 * ti[u] + q + 4 * v;
+          cv[u][v] = (ok[u] && row < nr && li < cmax) ? dst[u][(int64_t)(q + 4 * v) * n + li] : 0.0;
+        }
+      }
+      #pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (!ok[u]) continue;
+        d4 t = d4{0.0, 0.0, 0.0, 0.0};
+        #pragma unroll
+        for (int s = 0; s < kCb / 4; ++s) {
+          const double av = pan[(b + 16 * ti[u] + li) * kChPitch + 4 * s + q];
+          const double bw = ys[u] ? yb[(4 * s + q) * kChYPitch + 16 * tk[u] + li]
+                                  : pan[(b + 16 * tk[u] + li) * kChPitch + 4 * s + q];
+          t = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bw, t, 0, 0, 0);
+        }
+        const int cmax = ys[u] ? n : nr - b - 16 * tk[u];
+        #pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = b + 16 * ti[u] + q + 4 * v;
+          if (row < nr && li < cmax) dst[u][(int64_t)(q + 4 * v) * n + li] = cv[u][v] - t[v];
+        }
+      }
+    }
+    __syncthreads();
   }
 }
 
-// C[i][j] = beta C[i][j] + alpha sum_k A[i*ar + k*ac] B[k*br + j*bc], i < M, j < N
-// (lower != 0: only j <= i + diag).  One thread per element.
-__global__ void k_gemm_s(double* C, int ldc, const double* A, int64_t ar, int64_t ac,
-                         const double* B, int64_t br, int64_t bc, int M, int N, int K,
-                         double alpha, double beta, int lower, int diag) {
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (int64_t)M * N) return;
-  const int i = (int)(idx / N), j = (int)(idx % N);
-  if (lower && j > i + diag) return;
-  double s = 0.0;
-  #pragma unroll 8
-  for (int k = 0; k < K; ++k) s = __builtin_fma(A[i * ar + k * ac], B[k * br + j * bc], s);
-  double* c = C + (int64_t)i * ldc + j;
-  *c = (beta == 0.0 ? 0.0 : beta * *c) + alpha * s;
+size_t chol_lds_bytes() {
+  return sizeof(double) * ((size_t)kChRows * kChPitch + (size_t)kCb * kChPitch + kCb +
+                           (size_t)kCb * kChYPitch);
 }
 
-static hipError_t gemm_s(double* C, int ldc, const double* A, int64_t ar, int64_t ac,
-                         const double* B, int64_t br, int64_t bc, int M, int N, int K, double alpha,
-                         double beta, int lower, int diag, hipStream_t st) {
-  if (M <= 0 || N <= 0) return hipSuccess;
-  const int64_t tot = (int64_t)M * N;
-  hipLaunchKernelGGL(k_gemm_s, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, C, ldc, A, ar,
-                     ac, B, br, bc, M, N, K, alpha, beta, lower, diag);
+// S (n x n, overwritten with L: lower triangle, zero upper part of the
+// diagonal blocks), Linv (n x n, complete with zeros above the diagonal);
+// info[0] = 0 on entry.
+hipError_t launch_cholesky_inv(double* S, double* Linv, int n, int* info, hipStream_t st) {
+  if (n > kChRows) return hipErrorInvalidValue;
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_chol_inv, dim3(1), dim3(kChThreads), chol_lds_bytes(), st, S, Linv, n, info);
   return hipGetLastError();
-}
-
-__global__ void k_copy2d(double* __restrict__ dst, int ldd, const double* __restrict__ src, int lds,
-                         int M, int N) {
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (int64_t)M * N) return;
-  const int i = (int)(idx / N), j = (int)(idx % N);
-  dst[(int64_t)i * ldd + j] = src[(int64_t)i * lds + j];
 }
 
 __global__ void k_zero_upper_copy(const double* __restrict__ src, double* __restrict__ dst, int n) {
@@ -480,51 +613,6 @@ __global__ void k_zero_upper_copy(const double* __restrict__ src, double* __rest
   if (idx >= (int64_t)n * n) return;
   const int i = (int)(idx / n), k = (int)(idx % n);
   dst[idx] = (k <= i) ? src[idx] : 0.0;
-}
-
-// S (n x n, overwritten with L), Linv (n x n), T: n x n scratch, info[0] = 0 on entry.
-hipError_t launch_cholesky_inv(double* S, double* Linv, double* T, int n, int* info,
-                               hipStream_t st) {
-  if (n > 256) return hipErrorInvalidValue;
-  hipError_t e = launch_fill(Linv, (int64_t)n * n, 0.0, st);
-  if (e != hipSuccess) return e;
-  const int nb = (n + kCb - 1) / kCb;
-  for (int J = 0; J < nb; ++J) {
-    const int r0 = J * kCb, b = min(kCb, n - r0);
-    double* DJ = Linv + (int64_t)r0 * n + r0;
-    hipLaunchKernelGGL(k_potrf_block, dim3(1), dim3(256), 2 * kCb * (kCb + 1) * sizeof(double), st,
-                       S, n, r0, b, DJ, n, info);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    const int r1 = r0 + b, rem = n - r1;
-    if (rem <= 0) break;
-    // T = S[r1:, r0:r1] inv(L_JJ)^T; then copy back as the panel of L
-    e = gemm_s(T, b, S + (int64_t)r1 * n + r0, n, 1, DJ, 1, n, rem, b, b, 1.0, 0.0, 0, 0, st);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_copy2d, dim3((unsigned)((rem * b + 255) / 256)), dim3(256), 0, st,
-                       S + (int64_t)r1 * n + r0, n, (const double*)T, b, rem, b);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    // trailing lower triangle: S[r1:, r1:] -= P P^T, P = panel (rem x b)
-    e = gemm_s(S + (int64_t)r1 * n + r1, n, S + (int64_t)r1 * n + r0, n, 1,
-               S + (int64_t)r1 * n + r0, 1, n, rem, rem, b, -1.0, 1.0, 1, 0, st);
-    if (e != hipSuccess) return e;
-  }
-  return hipSuccess;
-}
-
-hipError_t launch_linv_offdiag(const double* L, double* Linv, double* T, int n, hipStream_t st) {
-  hipError_t e;
-  const int nb = (n + kCb - 1) / kCb;
-  for (int I = 1; I < nb; ++I) {
-    const int r0 = I * kCb, b = min(kCb, n - r0);
-    // T (b x r0) = L[r0:r0+b, 0:r0] Linv[0:r0, 0:r0]
-    e = gemm_s(T, r0, L + (int64_t)r0 * n, n, 1, Linv, n, 1, b, r0, r0, 1.0, 0.0, 0, 0, st);
-    if (e != hipSuccess) return e;
-    // Linv[r0:r0+b, 0:r0] = -inv(L_II) T
-    e = gemm_s(Linv + (int64_t)r0 * n, n, Linv + (int64_t)r0 * n + r0, n, 1, T, r0, 1, b, r0, b, -1.0,
-               0.0, 0, 0, st);
-    if (e != hipSuccess) return e;
-  }
-  return hipSuccess;
 }
 
 hipError_t launch_chol_factor(const double* S, const double* Linv, int norb, double* L,
