@@ -303,20 +303,27 @@ struct MfEngine {
   // rows of 4 (mod 32) doubles: the x-pass operand (16 rows x 4 columns) and
   // the tile stores fall on distinct banks
   __device__ __forceinline__ static int pitch(int m1) { return m1 + ((36 - (m1 & 31)) & 31); }
-  // tile t of this wave: output block k0 along the pass, line block o0
-  __device__ __forceinline__ static void tile_of(int t, int nbo, int& k0, int& o0) {
-    const int tile = (threadIdx.x >> 6) + t * kXyWaves;
-    const int bc = tile / nbo;
-    k0 = bc * 16;
-    o0 = (tile - bc * nbo) * 16;
-  }
-  // tile t of this wave in (y block, x block) order for both passes
-  __device__ __forceinline__ static void tile_of_yx(int t, int AX, int m1, int& k0, int& o0) {
-    const int tile = (threadIdx.x >> 6) + t * kXyWaves;
-    const int nbx = (m1 + 15) >> 4;
-    const int yb = tile / nbx, xb = tile - yb * nbx;
-    k0 = (AX == 1 ? xb : yb) * 16;
-    o0 = (AX == 1 ? yb : xb) * 16;
+  // The tiles of this wave, tile = wave + t kXyWaves = a n + b, stepped
+  // without a division per tile; the wave index is uniform, so this is
+  // scalar work.  Order (a, b) = (output block k0 along the pass, line block
+  // o0) with n = line blocks, or (y block, x block) with n = x blocks.
+  struct Walk {
+    int a, b, n, da, db;
+    __device__ __forceinline__ explicit Walk(int n_) : n(n_) {
+      const int wv = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+      a = wv / n;
+      b = wv - a * n;
+      da = kXyWaves / n;
+      db = kXyWaves - da * n;
+    }
+    __device__ __forceinline__ void next() {
+      b += db;
+      a += da;
+      if (b >= n) { b -= n; ++a; }
+    }
+  };
+  __device__ __forceinline__ static int wave_id() {
+    return __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
   }
   // One pass.  YX: tiles in (y block, x block) order; ACC: accumulate onto
   // r (the other pass's sums of the same elements); fscale multiplies the
@@ -337,25 +344,37 @@ struct MfEngine {
     #pragma unroll
     for (int s = 0; s < S; ++s) fc[s] = ft[s * 64 + lane] * fscale;
     if (!ACC) r.n = 0;
+    const int wv = wave_id();
+    Walk wk(YX ? (m1 + 15) >> 4 : nbo);
     #pragma unroll
     for (int t = 0; t < MT; ++t) {
-      if ((threadIdx.x >> 6) + t * kXyWaves >= nt) break;
+      if (wv + t * kXyWaves >= nt) break;
       if (!ACC) r.n = t + 1;
-      int k0, o0;
-      if (YX) tile_of_yx(t, AX, m1, k0, o0);
-      else tile_of(t, nbo, k0, o0);
+      const int k0 = (YX && AX == 1 ? wk.b : wk.a) * 16;
+      const int o0 = (YX && AX == 1 ? wk.a : wk.b) * 16;
+      wk.next();
       const int line = min(o0 + li, mo - 1);      // rows/columns past the end: unused outputs
       const V* lp = AX == 1 ? buf + line * pitch : buf + line;
-      // input index of step s: (k0 - OHI + 4 s + q) mod mc; lines are at
-      // least 4 long, so a step wraps at most once (branch-free)
-      int j = (k0 - OHI + q) % mc;
-      j = j < 0 ? j + mc : j;
+      // input index of step s: (k0 - OHI + 4 s + q) mod mc.  The window's
+      // start jb is uniform; a window that does not reach the end of the line
+      // is read at fixed strides, otherwise with a wrap per step (lines are
+      // at least 4 long, so a step wraps at most once)
+      int jb = k0 - OHI;
+      while (jb < 0) jb += mc;
       double x[S];
-      #pragma unroll
-      for (int s = 0; s < S; ++s) {
-        x[s] = lp[__mul24(j, es)];
-        j += 4;
+      if (jb + 4 * S <= mc) {
+        const V* p0 = lp + (jb + q) * es;
+        #pragma unroll
+        for (int s = 0; s < S; ++s) x[s] = p0[4 * s * es];
+      } else {
+        int j = jb + q;
         j = j >= mc ? j - mc : j;
+        #pragma unroll
+        for (int s = 0; s < S; ++s) {
+          x[s] = lp[__mul24(j, es)];
+          j += 4;
+          j = j >= mc ? j - mc : j;
+        }
       }
       d4 acc = {0.0, 0.0, 0.0, 0.0};
       if (ACC) acc = r.r[t];
@@ -372,11 +391,12 @@ struct MfEngine {
     const int lane = threadIdx.x & 63, li = lane & 15, q = lane >> 4;
     const int mc = AX == 1 ? m1 : m2, mo = AX == 1 ? m2 : m1;
     const int nbo = (mo + 15) >> 4;
+    Walk wk(nbo);
     #pragma unroll
     for (int t = 0; t < MT; ++t) {
       if (t >= r.n) break;
-      int k0, o0;
-      tile_of(t, nbo, k0, o0);
+      const int k0 = wk.a * 16, o0 = wk.b * 16;
+      wk.next();
       #pragma unroll
       for (int v = 0; v < 4; ++v) {
         // x-pass: row o0 + i, column k0 + n;  y-pass: row k0 + i, column o0 + n
