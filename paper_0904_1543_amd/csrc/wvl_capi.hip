@@ -1650,7 +1650,7 @@ int wvl_overlap(wvl_plan* p, const void* c, double* S, void* ws, void* stream) {
 }  // extern "C"
 
 // Overlap, Cholesky and X <- L^{-1} X with the scratch arrays given (SYRK
-// slice partials, L, L^{-1}, a product scratch).
+// slice partials, L, L^{-1}).
 static int orthonormalize_into(wvl_plan* p, void* c, double* S, double* L, double* syrk, double* Lw,
                                double* Li, hipStream_t st) {
   const size_t nn = sizeof(double) * (size_t)p->norb * p->norb;
