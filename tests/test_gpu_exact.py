@@ -144,7 +144,8 @@ def test_exact_engine_is_deterministic_and_graph_replays():
         assert torch.equal(rg["hpsi"], r1["hpsi"]) and torch.equal(rg["energies"], r1["energies"])
 
 
-PC_CASES = {"one_tile": (2, (8, 8, 8)), "nonsquare": (3, (16, 24, 8)), "tall": (2, (24, 16, 32))}
+PC_CASES = {"one_tile": (2, (8, 8, 8)), "single": (1, (8, 16, 8)), "nonsquare": (3, (16, 24, 8)),
+            "tall": (2, (24, 16, 32))}
 
 
 def _pc_run(plan, C, eps, iters, hg):

@@ -28,11 +28,13 @@ def test_overlap(prec, norb, dims):
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32c"])
-@pytest.mark.parametrize("norb,dims", [(6, (6, 5, 4)), (64, (8, 8, 8)), (33, (4, 4, 6)),
-                                       (100, (8, 8, 8)), (250, (4, 6, 6)), (256, (4, 4, 6))])
+@pytest.mark.parametrize("norb,dims", [(1, (4, 4, 4)), (6, (6, 5, 4)), (32, (4, 4, 4)),
+                                       (64, (8, 8, 8)), (33, (4, 4, 6)), (100, (8, 8, 8)),
+                                       (250, (4, 6, 6)), (256, (4, 4, 6))])
 def test_orthonormalize(prec, norb, dims):
-    """Cholesky blocks of 32: one partial block, a block of one row, several
-    panels with ragged 16-row tiles, the 256-orbital maximum."""
+    """Cholesky blocks of 32: a single orbital, one partial block, exactly one
+    block, a block of one row, several panels with ragged 16-row tiles, the
+    256-orbital maximum."""
     cs = inputs.random_case(19, norb, dims)
     C = cs["C"] + 0.3 * cs["C"][:1]
     plan = ops.Plan(cs["dims"], prec=prec)
