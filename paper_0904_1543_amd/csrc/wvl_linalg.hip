@@ -176,9 +176,11 @@ __global__ void k_syrk_reduce(const double* __restrict__ part, int norb, int nsl
 // buffered: the next chunk's loads are in flight while the current one is
 // multiplied), so HBM is read once; the lower triangle of S is cut into
 // 32 x 32 blocks, dealt to the waves round-robin, each a 2 x 2 set of 16 x 16
-// matrix-core tiles.  Lane group q of step s takes coefficient 4 q + s of the
-// chunk for both operands (the sum does not depend on the order).  Slice
-// partials are summed in slice order by k_syrk32_reduce.
+// matrix-core tiles (a diagonal block skips its tile above the diagonal,
+// which the reduction never reads).  Lane group q of step s takes
+// coefficient 4 q + s of the chunk for both operands (the sum does not
+// depend on the order).  Slice partials are summed in slice order by
+// k_syrk32_reduce.
 // ---------------------------------------------------------------------------
 constexpr int kS32Waves = 8;
 constexpr int kS32MaxBlocks = 5;     // ceil(36 / 8) blocks per wave at 256 orbitals
@@ -260,8 +262,10 @@ __global__ __launch_bounds__(512) void k_syrk32(const void* __restrict__ X, int6
         #pragma unroll
         for (int a = 0; a < 2; ++a)
           #pragma unroll
-          for (int c = 0; c < 2; ++c)
+          for (int c = 0; c < 2; ++c) {
+            if (I == J && a == 0 && c == 1) continue;   // above the diagonal: never read
             acc[m][a][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[c], acc[m][a][c], 0, 0, 0);
+          }
       }
     }
     if (more) put(buf ^ 1);
