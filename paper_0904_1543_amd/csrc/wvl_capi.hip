@@ -113,7 +113,7 @@ struct wvl_plan {
   // shared potential, lengths multiples of 16, isotropic grid spacing)
   bool oz_ok = false, use_oz = false;
   bool oz_pc = false;   // the preconditioner's operator with the exact products (no potential needed)
-  int oz_occ_xy = 2, oz_occ_z = 4;   // waves per SIMD of the plane and final kernels
+  int oz_occ_z = 4;   // waves per SIMD of the exact engine's final z kernel
   std::vector<int32_t> pxz;          // prefix of xz-planes (m2 per orbital)
   int32_t* d_pxz = nullptr;
   // persistent launches (WVL_PERSISTENT) of the plane path: work order by
@@ -484,7 +484,6 @@ int wvl_plan_create(wvl_ctx* ctx, const wvl_orbital* orbs, int32_t norb, int32_t
     p->oz_ok = ok;
     p->use_oz = ok;
     if (ok) p->variant = 3;
-    if (const char* o = getenv("WVL_EXACT_OCCUPANCY")) p->oz_occ_xy = atoi(o) == 4 ? 4 : 2;
     if (const char* o = getenv("WVL_EXACT_OCCUPANCY_Z")) p->oz_occ_z = atoi(o) == 2 ? 2 : 4;
     p->pxz.assign(norb + 1, 0);
     for (int b = 0; b < norb; ++b) p->pxz[b + 1] = p->pxz[b] + p->orbs[b].m[1];
@@ -931,7 +930,7 @@ int hpsi_oz(wvl_plan* p, hipStream_t st, const void* c, const double* V, double 
   }
   {
     Mark mk(p, st, ST_XY);
-    WVL_CHK(launch_oz_xy(a, p->oz_occ_xy, st));
+    WVL_CHK(launch_oz_xy(a, st));
   }
   if (rho || want_e) {
     Mark mk(p, st, ST_RHO);

@@ -228,7 +228,7 @@ bool oz_supported(int m1, int m2, int m3);
 hipError_t launch_oz_vprep(const double* V, int npl, int m3, float* vhl, int64_t M, int* vexp,
                            hipStream_t st);
 hipError_t launch_oz_z(const OzArgs& a, hipStream_t st);
-hipError_t launch_oz_xy(const OzArgs& a, int occ, hipStream_t st);
+hipError_t launch_oz_xy(const OzArgs& a, hipStream_t st);
 hipError_t launch_oz_zfinal(const OzArgs& a, int occ, hipStream_t st);
 
 size_t xy_lds_bytes(int prec, int m1, int m2, bool engine);

@@ -431,9 +431,8 @@ hipError_t launch_oz_z(const OzArgs& a, hipStream_t st) {
 }
 
 // one workgroup of 12 waves per CU (3 waves per SIMD)
-hipError_t launch_oz_xy(const OzArgs& a, int occ, hipStream_t st) {
+hipError_t launch_oz_xy(const OzArgs& a, hipStream_t st) {
   const OzLds l = oz_lds(a.m1, a.m2, a.m3);
-  (void)occ;
   hipLaunchKernelGGL(k_oz_xy<3>, dim3(a.m3 * a.ngroups), dim3(64 * kOzXyWaves), l.xy_bytes, st, a);
   return hipGetLastError();
 }

@@ -59,9 +59,10 @@ def test_exact_engine_against_oracle(case):
     _check(plan, cs, r, ref)
 
 
-@pytest.mark.parametrize("occ_xy", ["2", "4"])
-def test_exact_engine_both_occupancies(occ_xy, monkeypatch):
-    monkeypatch.setenv("WVL_EXACT_OCCUPANCY", occ_xy)
+@pytest.mark.parametrize("occ_z", ["2", "4"])
+def test_exact_engine_both_final_z_occupancies(occ_z, monkeypatch):
+    """The final z kernel at 2 and at 4 waves per SIMD (WVL_EXACT_OCCUPANCY_Z)."""
+    monkeypatch.setenv("WVL_EXACT_OCCUPANCY_Z", occ_z)
     cs = inputs.random_case(160, 3, (16, 24, 8), potential="gauss16")
     plan = ops.Plan(cs["dims"], prec="f32c")
     ref = W.local_hpsi(cs["C"], cs["V"], cs["occ"])
