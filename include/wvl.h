@@ -302,7 +302,9 @@ int wvl_plan_sync(wvl_plan *plan, void *stream);
  * WVL_AUTOTUNE the environment variable WVL_NO_PLANE_KERNEL forces 0,
  * WVL_F32C_VECTOR keeps WVL_F32C off variant 3 and WVL_XY_VECTOR forces 1
  * over 2; the variable WVL_PLANE_OCCUPANCY=2 compiles
- * the plane kernel's choice for 2 instead of 4 waves per SIMD,
+ * the plane kernel's choice for 2 instead of 4 waves per SIMD (where the
+ * float64 matrix-core form then keeps its density group's plane in LDS;
+ * WVL_NO_RHO_LDS keeps it in memory),
  * WVL_EXACT_OCCUPANCY_Z=2 the last z kernel of variant 3 for 2, and
  * WVL_NO_ZFUSE runs the last z step as two passes instead of one fused
  * launch (same results bit for bit; the fused launch is used for WVL_F64 and

@@ -29,17 +29,20 @@ def refs():
 
 
 @pytest.mark.parametrize("case", list(CASES))
-@pytest.mark.parametrize("form", ["f64", "f64_vector", "f64_occ2", "f32", "f32c"])
+@pytest.mark.parametrize("form", ["f64", "f64_vector", "f64_occ2", "f64_occ2_mem", "f32", "f32c"])
 def test_grouped_density_and_energies(refs, case, form, monkeypatch):
     prec = form.split("_")[0]
     if form == "f64_vector":
         monkeypatch.setenv("WVL_XY_VECTOR", "1")
-    if form == "f64_occ2":     # 2 waves per SIMD: the group's density plane kept in LDS
+    if form.startswith("f64_occ2"):   # 2 waves per SIMD: the group's density plane kept in LDS
         monkeypatch.setenv("WVL_PLANE_OCCUPANCY", "2")
+    if form == "f64_occ2_mem":        # ... or, at the same occupancy, in memory
+        monkeypatch.setenv("WVL_NO_RHO_LDS", "1")
     cs, ref = refs[case]
     plan = ops.Plan(cs["dims"], prec=prec)
     assert plan.query(lib.WVL_Q_GROUP) == EXPECT_G[case]
-    assert plan.query(lib.WVL_Q_VARIANT) == (2 if form in ("f64", "f64_occ2") else 1)
+    assert plan.query(lib.WVL_Q_VARIANT) == (2 if form.startswith("f64") and form != "f64_vector"
+                                             else 1)
     r = plan.local_hpsi(plan.pack(cs["C"]), plan.pack_potential(cs["V"]), per_orbital=True)
     tol = TOL[prec]
     assert_close(r["rho"].cpu().numpy(), ref["rho"].ravel(), tol, "rho")
