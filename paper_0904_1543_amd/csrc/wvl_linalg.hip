@@ -670,15 +670,25 @@ __global__ __launch_bounds__(512) void k_trmm2(const double* __restrict__ Li, co
   };
   // L^{-1} operands of chunk kc: lane (li, q) step s takes column 16 kc + 4 q + s
   double an[2][4];
+  // (the four values of a lane are consecutive in its row: two 16-byte loads
+  // when they are inside the matrix and n is even, so that they are aligned)
   auto fetch_a = [&](int kc) {
     #pragma unroll
     for (int a = 0; a < 2; ++a) {
       const int row = 16 * tiles[a] + li;
-      #pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        const int k = 16 * kc + 4 * q + s;
-        an[a][s] = (tiles[a] >= kc && tiles[a] < ntile && row < n && k < n) ? Li[(int64_t)row * n + k]
-                                                                             : 0.0;
+      const int k = 16 * kc + 4 * q;
+      const bool act = tiles[a] >= kc && tiles[a] < ntile;
+      if (act && row < n && k + 4 <= n && (n & 1) == 0) {
+        const double2* p = reinterpret_cast<const double2*>(Li + (int64_t)row * n + k);
+        const double2 x0 = p[0], x1 = p[1];
+        an[a][0] = x0.x;
+        an[a][1] = x0.y;
+        an[a][2] = x1.x;
+        an[a][3] = x1.y;
+      } else {
+        #pragma unroll
+        for (int s = 0; s < 4; ++s)
+          an[a][s] = (act && row < n && k + s < n) ? Li[(int64_t)row * n + k + s] : 0.0;
       }
     }
   };
